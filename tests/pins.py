@@ -1,0 +1,309 @@
+"""Checks that pin the CPU oracle to what the paper and plain mathematics fix.
+
+Each check takes an ``oracle.Oracle`` so the same checks can be run against
+deliberately broken builds of the oracle (tests/test_oracle_mutants.py): a
+plausible mistake anywhere in the oracle must make at least one of them fail.
+Nothing here calls the GPU library.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+# ---------------------------------------------------------------------------
+# brute-force helpers written only here (independent of the oracle)
+# ---------------------------------------------------------------------------
+
+def all_vertices(d: int, x: int) -> np.ndarray:
+    """Every {x,d} EVP vertex (Sec. 2.3): x non-zero places, each +-1."""
+    out = []
+    for places in itertools.combinations(range(d), x):
+        for signs in itertools.product((-1, 1), repeat=x):
+            v = [0] * d
+            for p, s in zip(places, signs):
+                v[p] = s
+            out.append(v)
+    return np.array(out, dtype=np.int8)
+
+
+def bit_b2sp(cq: np.ndarray, cv: np.ndarray, W: int) -> np.ndarray:
+    """b2sp of Sec. 5.1.2 written straight from the packed bit planes with
+    Python integer popcounts: (bsp(+,+) + bsp(-,-)) - (bsp(+,-) + bsp(-,+))."""
+    def plane(c, off):
+        return [int.from_bytes(np.ascontiguousarray(r[off:off + W]).astype("<u4").tobytes(), "little")
+                for r in c]
+    qp, qm, vp, vm = plane(cq, 0), plane(cq, W), plane(cv, 0), plane(cv, W)
+    out = np.empty((len(qp), len(vp)), dtype=np.int64)
+    for a in range(len(qp)):
+        for b in range(len(vp)):
+            bsp = lambda s, t: bin(s & t).count("1")
+            out[a, b] = (bsp(qp[a], vp[b]) + bsp(qm[a], vm[b])) - (bsp(qp[a], vm[b]) + bsp(qm[a], vp[b]))
+    return out
+
+
+def lexsort_topk(scores_row: np.ndarray, k: int):
+    """Nearest first: larger score first, then lower id (np.lexsort brute force)."""
+    ids = np.arange(scores_row.shape[0])
+    order = np.lexsort((ids, -scores_row.astype(np.int64)))
+    return order[:k].astype(np.int32), scores_row[order[:k]].astype(np.int32)
+
+
+# ---------------------------------------------------------------------------
+# encode (Sec. 2.4)
+# ---------------------------------------------------------------------------
+
+def check_table3_encode(o):
+    g = golden("table3_worked_example.json")
+    V = o.encode(np.array([g["u1"], g["u2"]], dtype=np.float32), g["x"])
+    assert V[0].tolist() == g["v1_printed"], "Table 3: v1 must match the printed vertex"
+    sel = sorted(np.nonzero(V[1])[0].tolist())
+    assert sel == g["u2_highlighted"], "Table 3: u2's highlighted cells are its x largest"
+    # the four signs the table prints consistently; index 8 is the erratum
+    for i in (1, 2, 3, 6):
+        assert V[1][i] == g["v2_printed"][i]
+    assert V[1][8] == 1, "u2[8] = +0.4 is positive, so its vertex coordinate is +1"
+
+
+def check_enumeration_argmax(o, seed=1):
+    """Sec. 2.4: the nearest vertex maximises the scalar product. For every d<=10
+    and every x, the encoding is an argmax over all C(d,x)*2^x vertices, and is
+    the argmax when that is unique."""
+    rng = np.random.default_rng(seed)
+    for d in range(1, 11):
+        for x in range(1, d + 1):
+            verts = all_vertices(d, x)
+            assert verts.shape[0] == math.comb(d, x) * 2 ** x
+            U = rng.standard_normal((6, d)).astype(np.float32)
+            V = o.encode(U, x)
+            for u, v in zip(U, V):
+                s = verts.astype(np.float64) @ u.astype(np.float64)
+                best = s.max()
+                mine = float(v.astype(np.float64) @ u.astype(np.float64))
+                assert mine == best, f"d={d} x={x}: encoding is not the nearest vertex"
+                winners = np.nonzero(s == best)[0]
+                if winners.size == 1:
+                    assert np.array_equal(verts[winners[0]], v)
+
+
+def check_fig2_cuboctahedron(o, seed=2):
+    g = golden("fig2_cuboctahedron.json")
+    printed = sorted(tuple(v) for v in g["vertices"])
+    assert sorted(tuple(v) for v in all_vertices(3, 2).tolist()) == printed
+    rng = np.random.default_rng(seed)
+    U = rng.standard_normal((3000, 3)).astype(np.float32)
+    seen = {tuple(r) for r in o.encode(U, 2).tolist()}
+    assert sorted(seen) == printed, "random points land on exactly the 12 printed vertices"
+
+
+def check_special_cases(o, seed=3):
+    rng = np.random.default_rng(seed)
+    U = rng.standard_normal((50, 37)).astype(np.float32)
+    # x = d: the sign vector, i.e. 1-bit quantisation (Sec. 4.2: {d,d} EVP)
+    Vd = o.encode(U, 37)
+    assert np.array_equal(Vd, np.where(U < 0, -1, 1).astype(np.int8))
+    # x = 1: signed one-hot at the largest magnitude
+    V1 = o.encode(U, 1)
+    am = np.argmax(np.abs(U), axis=1)
+    exp = np.zeros_like(V1)
+    exp[np.arange(50), am] = np.where(U[np.arange(50), am] < 0, -1, 1)
+    assert np.array_equal(V1, exp)
+
+
+def check_invariants(o, seed=4):
+    rng = np.random.default_rng(seed)
+    for d, x in ((1, 1), (31, 7), (32, 32), (33, 11), (100, 67), (384, 96)):
+        U = rng.standard_normal((40, d)).astype(np.float32)
+        V = o.encode(U, x)
+        assert np.all(np.count_nonzero(V, axis=1) == x), "exactly x non-zeros"
+        assert set(np.unique(V).tolist()) <= {-1, 0, 1}
+        # positive scaling by a power of two does not move the vertex
+        assert np.array_equal(o.encode(U * np.float32(8.0), x), V)
+        # reflection through the origin reflects the vertex (no zeros here)
+        assert np.array_equal(o.encode(-U, x), -V)
+
+
+def check_ties_and_zeros(o):
+    # equal magnitudes at the cut: lower index wins
+    V = o.encode(np.array([[0.5, -0.5, 0.5, 0.25]], np.float32), 2)
+    assert V[0].tolist() == [1, -1, 0, 0]
+    V = o.encode(np.array([[0.25, 0.5, -0.5, 0.5, 0.5]], np.float32), 3)
+    assert V[0].tolist() == [0, 1, -1, 1, 0]
+    # selected zeros, including -0.0, get +1 (negative iff u < 0)
+    V = o.encode(np.array([[0.0, -0.0, 0.0, 1.0]], np.float32), 3)
+    assert V[0].tolist() == [1, 1, 0, 1]
+    # subnormals keep their order and sign
+    tiny = np.float32(1e-45)
+    V = o.encode(np.array([[tiny, -tiny * 3, 0.0, -tiny * 2]], np.float32), 2)
+    assert V[0].tolist() == [0, -1, 0, -1]
+    V = o.encode(np.array([[0.0, -tiny, 0.0, 0.0]], np.float32), 2)
+    assert V[0].tolist() == [1, -1, 0, 0]
+
+
+# ---------------------------------------------------------------------------
+# bit planes (Sec. 5.1.2, Table 3)
+# ---------------------------------------------------------------------------
+
+def _bits_from_word_rows(C, W, d):
+    plus = [(int(C[w]) >> b) & 1 for w in range(W) for b in range(32)][:d]
+    minus = [(int(C[W + w]) >> b) & 1 for w in range(W) for b in range(32)][:d]
+    return plus, minus
+
+
+def check_table3_pack(o):
+    g = golden("table3_worked_example.json")
+    W = o.words_per_plane(10)
+    assert W == 1
+    for v, vp, vm in (("v1_printed", "v1_plus_printed", "v1_minus_printed"),
+                      ("v2_printed", "v2_plus_printed", "v2_minus_printed")):
+        C = o.pack(np.array([g[v]], np.int8))
+        plus, minus = _bits_from_word_rows(C[0], W, 10)
+        assert plus == g[vp] and minus == g[vm], f"Table 3 bit rows of {v}"
+
+
+def check_pack_layout(o, seed=5):
+    rng = np.random.default_rng(seed)
+    for d in (1, 5, 32, 33, 64, 100, 384):
+        W = o.words_per_plane(d)
+        assert W == (d + 31) // 32
+        V = rng.integers(-1, 2, size=(20, d)).astype(np.int8)
+        C = o.pack(V)
+        assert C.shape == (20, 2 * W)
+        for r in range(20):
+            plus, minus = _bits_from_word_rows(C[r], W, d)
+            assert plus == (V[r] == 1).astype(int).tolist()
+            assert minus == (V[r] == -1).astype(int).tolist()
+        assert np.all((C[:, :W] & C[:, W:]) == 0)
+        if d % 32:
+            pad = np.uint32((0xFFFFFFFF << (d % 32)) & 0xFFFFFFFF)
+            assert np.all((C[:, W - 1] & pad) == 0) and np.all((C[:, 2 * W - 1] & pad) == 0)
+        assert np.array_equal(o.unpack(C, d), V), "pack/unpack round trip"
+
+
+# ---------------------------------------------------------------------------
+# Delta = b2sp (Sec. 5.1.2)
+# ---------------------------------------------------------------------------
+
+def check_table3_delta(o):
+    g = golden("table3_worked_example.json")
+    v1 = np.array([g["v1_printed"]], np.int8)
+    v2p = np.array([g["v2_printed"]], np.int8)
+    v2 = o.encode(np.array([g["u2"]], np.float32), g["x"])
+    assert int(o.delta(v1, v2p)[0, 0]) == g["delta_v1_v2"]
+    assert int(o.delta(v1, v2)[0, 0]) == g["delta_v1_v2"]
+
+
+def check_delta_identities(o, seed=6):
+    rng = np.random.default_rng(seed)
+    d, x = 100, 67
+    V = o.encode(rng.standard_normal((60, d)).astype(np.float32), x)
+    D = o.delta(V, V)
+    assert np.all(np.diag(D) == x), "Delta(v,v) = x"
+    assert np.array_equal(D, D.T), "symmetry"
+    assert np.all(np.abs(D) <= x)
+    assert np.all(np.diag(o.delta(V, -V)) == -x), "Delta(v,-v) = -x"
+    # squared vertex distance 2x - 2 Delta is the squared Euclidean distance
+    Vf = V.astype(np.float64)
+    sq = ((Vf[:, None, :] - Vf[None, :, :]) ** 2).sum(-1)
+    assert np.array_equal(sq, 2 * x - 2 * D.astype(np.float64))
+    # library routine: an FP64 product of ternary matrices is exact here
+    assert np.array_equal((Vf @ Vf.T).astype(np.int64), D.astype(np.int64))
+
+
+def check_delta_one_bit_hamming(o, seed=7):
+    """x = d: Delta = d - 2 * Hamming distance of the sign bits (Sec. 4.2)."""
+    rng = np.random.default_rng(seed)
+    d = 77
+    U = rng.standard_normal((30, d)).astype(np.float32)
+    V = o.encode(U, d)
+    D = o.delta(V, V)
+    neg = V < 0
+    ham = (neg[:, None, :] != neg[None, :, :]).sum(-1)
+    assert np.array_equal(D, d - 2 * ham)
+
+
+def check_delta_bitwise(o, seed=8):
+    rng = np.random.default_rng(seed)
+    for d in (10, 33, 96):
+        W = o.words_per_plane(d)
+        Q = rng.integers(-1, 2, size=(5, d)).astype(np.int8)
+        V = rng.integers(-1, 2, size=(9, d)).astype(np.int8)
+        assert np.array_equal(o.delta(Q, V).astype(np.int64), bit_b2sp(o.pack(Q), o.pack(V), W))
+
+
+# ---------------------------------------------------------------------------
+# top-k (exhaustive kNN, Sec. 1.1 / Table 1; "closest n", Sec. 5.3)
+# ---------------------------------------------------------------------------
+
+def check_knn_bruteforce(o, seed=9):
+    rng = np.random.default_rng(seed)
+    for n, d, x, k in ((50, 16, 5, 7), (300, 40, 10, 30), (64, 8, 2, 64)):
+        V = o.encode(rng.standard_normal((n, d)).astype(np.float32), x)
+        Q = o.encode(rng.standard_normal((6, d)).astype(np.float32), x)
+        ids, sc = o.knn(Q, V, k)
+        D = (Q.astype(np.int64) @ V.astype(np.int64).T)
+        for q in range(Q.shape[0]):
+            ei, es = lexsort_topk(D[q], k)
+            assert np.array_equal(ids[q], ei) and np.array_equal(sc[q], es)
+
+
+def check_knn_ties(o, seed=10):
+    """Many exact ties: duplicated database codes; lower id must win."""
+    rng = np.random.default_rng(seed)
+    base = o.encode(rng.standard_normal((5, 24)).astype(np.float32), 6)
+    V = base[rng.integers(0, 5, size=400)]
+    Q = base[:3]
+    k = 50
+    ids, sc = o.knn(Q, V, k)
+    D = Q.astype(np.int64) @ V.astype(np.int64).T
+    for q in range(3):
+        assert np.all(np.diff(sc[q]) <= 0)
+        for j in range(k - 1):
+            if sc[q][j] == sc[q][j + 1]:
+                assert ids[q][j] < ids[q][j + 1]
+        chosen = set(ids[q].tolist())
+        kth = (int(sc[q][-1]), -int(ids[q][-1]))
+        for i in range(400):
+            if i not in chosen:
+                assert (int(D[q, i]), -i) < kth, "an excluded id beats the k-th result"
+        ei, es = lexsort_topk(D[q], k)
+        assert np.array_equal(ids[q], ei)
+
+
+def check_knn_shard_merge(o, seed=11):
+    """Order independence of the total-order key: top-k of shard top-ks."""
+    rng = np.random.default_rng(seed)
+    n, d, x, k = 700, 48, 20, 25
+    V = o.encode(rng.standard_normal((n, d)).astype(np.float32), x)
+    Q = o.encode(rng.standard_normal((4, d)).astype(np.float32), x)
+    full_i, full_s = o.knn(Q, V, k)
+    cuts = [0, 90, 91, 400, n]
+    cand_i, cand_s = [], []
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        kk = min(k, b - a)
+        i, s = o.knn(Q, V[a:b], kk)
+        cand_i.append(i + a)
+        cand_s.append(s)
+    ci, cs = np.concatenate(cand_i, 1), np.concatenate(cand_s, 1)
+    for q in range(4):
+        order = np.lexsort((ci[q], -cs[q].astype(np.int64)))[:k]
+        assert np.array_equal(ci[q][order], full_i[q]) and np.array_equal(cs[q][order], full_s[q])
+
+
+ALL_CHECKS = [
+    check_table3_encode, check_enumeration_argmax, check_fig2_cuboctahedron, check_special_cases,
+    check_invariants, check_ties_and_zeros, check_table3_pack, check_pack_layout, check_table3_delta,
+    check_delta_identities, check_delta_one_bit_hamming, check_delta_bitwise, check_knn_bruteforce,
+    check_knn_ties, check_knn_shard_merge,
+]
