@@ -1,0 +1,406 @@
+// api.cpp -- the C ABI of include/tq.h: argument checks, device contexts,
+// database lifetime, search dispatch and kernel timing.  All GPU work is done
+// by the kernels in the .hip files; this file only validates and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <utility>
+#include <vector>
+
+#include "tq.h"
+#include "tq_internal.h"
+#include "tq_runtime.h"
+
+// ---------------------------------------------------------------------------
+// errors and logging
+// ---------------------------------------------------------------------------
+
+namespace tqr {
+
+static thread_local std::string t_last_error;
+
+int log_level() {
+  static int level = [] {
+    const char *e = std::getenv("TQ_LOG");
+    return e ? std::atoi(e) : 0;
+  }();
+  return level;
+}
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  t_last_error = buf;
+  if (log_level() >= 1) std::fprintf(stderr, "[tq] %s: %s\n", tq_status_str(code), buf);
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(e == hipErrorOutOfMemory ? TQ_ERR_NOMEM : TQ_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+void clear_error() { t_last_error.clear(); }
+
+// ---------------------------------------------------------------------------
+// per-device context
+// ---------------------------------------------------------------------------
+
+namespace {
+constexpr int kMaxDevices = 64;
+DevCtx g_dev[kMaxDevices];
+std::mutex g_dev_mu;
+}  // namespace
+
+int current_device(int *dev) {
+  hipError_t e = hipGetDevice(dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (*dev < 0 || *dev >= kMaxDevices) return fail(TQ_ERR_DEVICE, "device index %d out of range", *dev);
+  return TQ_OK;
+}
+
+int device_ctx(int dev, DevCtx **out) {
+  std::lock_guard<std::mutex> g(g_dev_mu);
+  DevCtx &c = g_dev[dev];
+  if (!c.ready) {
+    int cu = 0;
+    hipError_t e = hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+    e = hipMalloc(&c.flags, 256);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(flags)");
+    e = hipMemset(c.flags, 0, 256);
+    if (e != hipSuccess) return hip_fail(e, "hipMemset(flags)");
+    c.num_cu = cu;
+    c.ready = true;
+  }
+  *out = &c;
+  return TQ_OK;
+}
+
+DeviceGuard::DeviceGuard(int dev) {
+  if (hipGetDevice(&prev_) == hipSuccess && prev_ != dev) {
+    if (hipSetDevice(dev) == hipSuccess) switched_ = true;
+  }
+}
+DeviceGuard::~DeviceGuard() {
+  if (switched_) (void)hipSetDevice(prev_);
+}
+
+// ---------------------------------------------------------------------------
+// kernel timing (HIP events around scan launches, on the launch stream)
+// ---------------------------------------------------------------------------
+
+namespace {
+struct Timing {
+  std::mutex mu;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[2];
+  double total_ms[2] = {0, 0};
+  int64_t launches[2] = {0, 0};
+};
+Timing g_timing;
+std::atomic<int> g_timing_on{0};
+
+hipEvent_t pooled_event() {
+  if (!g_timing.pool.empty()) {
+    hipEvent_t e = g_timing.pool.back();
+    g_timing.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+}  // namespace
+
+TimedLaunch::TimedLaunch(int family, hipStream_t s) : family_(family), s_(s) {
+  if (!g_timing_on.load(std::memory_order_relaxed)) return;
+  std::lock_guard<std::mutex> g(g_timing.mu);
+  a_ = pooled_event();
+  b_ = pooled_event();
+  if (a_ && b_) hipEventRecord(a_, s_);
+}
+
+TimedLaunch::~TimedLaunch() {
+  if (!a_ || !b_) return;
+  std::lock_guard<std::mutex> g(g_timing.mu);
+  hipEventRecord(b_, s_);
+  g_timing.pending[family_].emplace_back(a_, b_);
+}
+
+// ---------------------------------------------------------------------------
+// scratch buffers
+// ---------------------------------------------------------------------------
+
+int scratch_get(ScratchMap &map, hipStream_t s, size_t bytes, void **out) {
+  Scratch &sc = map[s];
+  if (sc.bytes < bytes) {
+    if (sc.p) {
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(sc.p);
+      sc.p = nullptr;
+      sc.bytes = 0;
+    }
+    hipError_t e = hipMalloc(&sc.p, bytes);
+    if (e != hipSuccess) {
+      sc.p = nullptr;
+      return hip_fail(e, "hipMalloc(scratch)");
+    }
+    sc.bytes = bytes;
+  }
+  *out = sc.p;
+  return TQ_OK;
+}
+
+void scratch_free_all(ScratchMap &map) {
+  for (auto &kv : map)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  map.clear();
+}
+
+// ---------------------------------------------------------------------------
+// code validation (exactly x non-zeros, disjoint planes, zero padding)
+// ---------------------------------------------------------------------------
+
+int count_bad_codes(const uint32_t *codes, int64_t n, int d, int x, hipStream_t s, unsigned long long *bad) {
+  unsigned long long *dcount = nullptr;
+  hipError_t e = hipMalloc(&dcount, sizeof *dcount);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(counter)");
+  unsigned long long h = 0;
+  e = hipMemcpyAsync(dcount, &h, sizeof h, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = tqi::validate_launch(codes, n, d, x, dcount, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&h, dcount, sizeof h, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(dcount);
+  if (e != hipSuccess) return hip_fail(e, "code validation");
+  *bad = h;
+  return TQ_OK;
+}
+
+}  // namespace tqr
+
+using namespace tqr;
+
+// ---------------------------------------------------------------------------
+// public ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char *tq_status_str(int status) {
+  switch (status) {
+    case TQ_OK: return "TQ_OK";
+    case TQ_ERR_INVALID: return "TQ_ERR_INVALID";
+    case TQ_ERR_NOMEM: return "TQ_ERR_NOMEM";
+    case TQ_ERR_DEVICE: return "TQ_ERR_DEVICE";
+    case TQ_ERR_AGAIN: return "TQ_ERR_AGAIN";
+    case TQ_ERR_NOTFOUND: return "TQ_ERR_NOTFOUND";
+    case TQ_ERR_STATE: return "TQ_ERR_STATE";
+    default: return "TQ_ERR_UNKNOWN";
+  }
+}
+
+const char *tq_last_error(void) { return t_last_error.c_str(); }
+
+int tq_version(void) { return 10000; }
+
+int tq_code_words(int d) {
+  if (d < 1 || d > TQ_MAX_D) return fail(TQ_ERR_INVALID, "d=%d outside [1, %d]", d, TQ_MAX_D);
+  return (d + 31) / 32;
+}
+
+int tq_encode(const float *X, int64_t n, int d, int x, uint32_t *codes, void *stream) {
+  clear_error();
+  if (n < 0) return fail(TQ_ERR_INVALID, "n=%lld < 0", (long long)n);
+  if (d < 1 || d > TQ_MAX_D) return fail(TQ_ERR_INVALID, "d=%d outside [1, %d]", d, TQ_MAX_D);
+  if (x < 1 || x > d) return fail(TQ_ERR_INVALID, "x=%d outside [1, d=%d]", x, d);
+  if (n == 0) return TQ_OK;
+  if (!X || !codes) return fail(TQ_ERR_INVALID, "null X or codes");
+  int dev;
+  int rc = current_device(&dev);
+  if (rc) return rc;
+  DevCtx *ctx;
+  if ((rc = device_ctx(dev, &ctx))) return rc;
+  hipError_t e = tqi::encode_launch(X, n, d, x, codes, ctx->flags, ctx->num_cu, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "encode launch");
+  return TQ_OK;
+}
+
+int tq_sync(void *stream) {
+  clear_error();
+  int dev;
+  int rc = current_device(&dev);
+  if (rc) return rc;
+  DevCtx *ctx;
+  if ((rc = device_ctx(dev, &ctx))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  int flag = 0;
+  e = hipMemcpy(&flag, ctx->flags, sizeof flag, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "reading device flags");
+  if (flag) {
+    int zero = 0;
+    e = hipMemcpy(ctx->flags, &zero, sizeof zero, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "clearing device flags");
+    if (flag & 1) return fail(TQ_ERR_INVALID, "tq_encode saw a NaN or infinite input (row code set to zero)");
+  }
+  return TQ_OK;
+}
+
+int tq_db_create(const uint32_t *codes, int64_t n, int d, int x, void *stream, tq_db **out) {
+  clear_error();
+  if (!out) return fail(TQ_ERR_INVALID, "null out");
+  *out = nullptr;
+  if (!codes) return fail(TQ_ERR_INVALID, "null codes");
+  if (n < 1 || n > INT32_MAX) return fail(TQ_ERR_INVALID, "n=%lld outside [1, 2^31)", (long long)n);
+  if (d < 1 || d > TQ_MAX_D) return fail(TQ_ERR_INVALID, "d=%d outside [1, %d]", d, TQ_MAX_D);
+  if (x < 1 || x > d) return fail(TQ_ERR_INVALID, "x=%d outside [1, d=%d]", x, d);
+  int dev;
+  int rc = current_device(&dev);
+  if (rc) return rc;
+  DevCtx *ctx;
+  if ((rc = device_ctx(dev, &ctx))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  unsigned long long bad = 0;
+  if ((rc = count_bad_codes(codes, n, d, x, s, &bad))) return rc;
+  if (bad) return fail(TQ_ERR_INVALID, "%llu of %lld code rows are not {%d,%d} EVP vertices", bad, (long long)n, x, d);
+
+  tq_db *db = new (std::nothrow) tq_db();
+  if (!db) return fail(TQ_ERR_NOMEM, "host allocation");
+  db->device = dev;
+  db->num_cu = ctx->num_cu;
+  const int W = (d + 31) / 32;
+  const int nc = (W + 3) / 4;
+  const int64_t ntiles = (n + tqi::kTileVecs - 1) / tqi::kTileVecs;
+  db->bytes = static_cast<size_t>(ntiles) * 2 * nc * 64 * sizeof(uint4);
+  uint4 *tiles = nullptr;
+  hipError_t e = hipMalloc(&tiles, db->bytes);
+  if (e != hipSuccess) {
+    delete db;
+    return hip_fail(e, "hipMalloc(database)");
+  }
+  e = tqi::repack_launch(codes, n, d, tiles, ntiles, nc, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipFree(tiles);
+    delete db;
+    return hip_fail(e, "database repack");
+  }
+  db->dev = tqi::DbDev{tiles, n, ntiles, d, x, W, nc};
+  *out = db;
+  return TQ_OK;
+}
+
+int tq_db_export(const tq_db *db, uint32_t *codes, void *stream) {
+  clear_error();
+  if (!db || !codes) return fail(TQ_ERR_INVALID, "null db or codes");
+  DeviceGuard g(db->device);
+  hipError_t e = tqi::export_launch(db->dev, codes, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "export launch");
+  return TQ_OK;
+}
+
+int tq_db_info(const tq_db *db, int64_t *n, int *d, int *x, size_t *device_bytes) {
+  clear_error();
+  if (!db) return fail(TQ_ERR_INVALID, "null db");
+  if (n) *n = db->dev.n;
+  if (d) *d = db->dev.d;
+  if (x) *x = db->dev.x;
+  if (device_bytes) *device_bytes = db->bytes;
+  return TQ_OK;
+}
+
+int tq_db_destroy(tq_db *db) {
+  clear_error();
+  if (!db) return TQ_OK;
+  {
+    DeviceGuard g(db->device);
+    std::lock_guard<std::mutex> l(db->mu);
+    scratch_free_all(db->scratch);
+    batched_release(db);
+    if (db->dev.tiles) (void)hipFree(const_cast<uint4 *>(db->dev.tiles));
+  }
+  delete db;
+  return TQ_OK;
+}
+
+int tq_search_knn(const tq_db *cdb, const uint32_t *qcodes, int nq, int k, int32_t *ids, int32_t *scores,
+                  const tq_search_opts *opts, void *stream) {
+  clear_error();
+  tq_db *db = const_cast<tq_db *>(cdb);
+  if (!db) return fail(TQ_ERR_INVALID, "null db");
+  if (!qcodes || !ids || !scores) return fail(TQ_ERR_INVALID, "null qcodes, ids or scores");
+  if (nq < 1) return fail(TQ_ERR_INVALID, "nq=%d < 1", nq);
+  if (k < 1 || k > TQ_MAX_K || k > db->dev.n)
+    return fail(TQ_ERR_INVALID, "k=%d outside [1, min(n=%lld, %d)]", k, (long long)db->dev.n, TQ_MAX_K);
+  const int path = opts ? opts->path : TQ_PATH_AUTO;
+  if (path < TQ_PATH_AUTO || path > TQ_PATH_BATCHED) return fail(TQ_ERR_INVALID, "unknown path %d", path);
+  if (opts && (opts->grid < 0 || opts->qtile < 0)) return fail(TQ_ERR_INVALID, "negative grid or qtile");
+  DeviceGuard g(db->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int rc;
+  if (opts && opts->check_queries) {
+    unsigned long long bad = 0;
+    if ((rc = count_bad_codes(qcodes, nq, db->dev.d, db->dev.x, s, &bad))) return rc;
+    if (bad)
+      return fail(TQ_ERR_INVALID, "%llu of %d query codes are not {%d,%d} EVP vertices", bad, nq, db->dev.x,
+                  db->dev.d);
+  }
+  std::lock_guard<std::mutex> l(db->mu);
+  const int use = choose_path(db, path, nq, k);
+  if (use == TQ_PATH_BATCHED) return search_batched(db, qcodes, nq, k, ids, scores, opts, s);
+  return search_plain(db, qcodes, nq, k, ids, scores, opts ? opts->grid : 0, s);
+}
+
+int tq_delta_dump(const tq_db *db, const uint32_t *qcodes, int nq, int32_t *delta, void *stream) {
+  clear_error();
+  if (!db || !qcodes || !delta) return fail(TQ_ERR_INVALID, "null db, qcodes or delta");
+  if (nq < 1 || nq > 65535) return fail(TQ_ERR_INVALID, "nq=%d outside [1, 65535]", nq);
+  DeviceGuard g(db->device);
+  hipError_t e = tqi::delta_dump_launch(db->dev, qcodes, nq, delta, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "delta dump launch");
+  return TQ_OK;
+}
+
+int tq_timing_enable(int enable) {
+  clear_error();
+  g_timing_on.store(enable ? 1 : 0);
+  return TQ_OK;
+}
+
+int tq_timing_read(int which, double *total_ms, int64_t *launches, int reset) {
+  clear_error();
+  if (which < 0 || which > 1) return fail(TQ_ERR_INVALID, "timing family %d", which);
+  std::lock_guard<std::mutex> g(g_timing.mu);
+  for (auto &pr : g_timing.pending[which]) {
+    float ms = 0.f;
+    if (hipEventSynchronize(pr.second) == hipSuccess && hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+      g_timing.total_ms[which] += ms;
+      g_timing.launches[which] += 1;
+    }
+    g_timing.pool.push_back(pr.first);
+    g_timing.pool.push_back(pr.second);
+  }
+  g_timing.pending[which].clear();
+  if (total_ms) *total_ms = g_timing.total_ms[which];
+  if (launches) *launches = g_timing.launches[which];
+  if (reset) {
+    g_timing.total_ms[which] = 0;
+    g_timing.launches[which] = 0;
+  }
+  return TQ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,179 @@
+// scan.hip -- exhaustive kNN of one query over the resident database with the
+// b2sp / Delta proxy (Sec. 5.1.2), and the per-query top-k merge.
+//
+// Plain single-query scan: the database is streamed once per query.  Work is
+// split in tiles of 64 vectors; wave w of the grid takes tiles w, w + #waves,
+// w + 2 #waves, ..., so at any moment the whole grid sweeps one contiguous
+// window of memory (the access order that reaches the highest HBM read rate).
+// A lane scores its tile vector against the query, whose nz / ng words sit in
+// scalar registers; the wave keeps its best k keys in a register list and only
+// offers keys above its current k-th key, so insertions are rare.  At the end
+// the workgroup's wave lists are tree-merged in LDS and written out; a second
+// kernel merges the workgroup lists of every query into ids and scores.
+#include "tq_device.h"
+
+namespace tqi {
+namespace {
+
+constexpr int kScanWaves = 4;
+constexpr int kScanBlock = 64 * kScanWaves;
+
+template <int NC, int R>
+__global__ __launch_bounds__(kScanBlock) void scan_plain_kernel(const uint4 *__restrict__ tiles, int64_t n,
+                                                               int64_t ntiles, int W,
+                                                               const uint32_t *__restrict__ qcode, int k,
+                                                               uint64_t *__restrict__ partial) {
+  __shared__ uint64_t lds[2][kScanWaves * 64 * R];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t nwaves = static_cast<int64_t>(gridDim.x) * kScanWaves;
+
+  QueryWords<NC> q;
+  q.load(qcode, W);
+
+  WaveList<R> list;
+  list.clear();
+  uint64_t thr = 0;
+  const int km1 = k - 1;
+
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * kScanWaves + wave; t < ntiles; t += nwaves) {
+    const int32_t delta = tile_delta<NC>(tiles + t * (2 * NC * 64), lane, q);
+    const int64_t id = t * 64 + lane;
+    const uint64_t key = make_key(delta, static_cast<uint32_t>(id));
+    offer_keys<R>(list, thr, key, id < n, km1, lane);
+  }
+
+  // workgroup merge of the wave lists (positions 0 .. k-1 of each)
+  uint64_t *a = lds[0];
+  uint64_t *b = lds[1];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int p = r * 64 + lane;
+    if (p < k) a[wave * k + p] = list.v[r];
+  }
+  uint64_t *res = tree_merge(a, b, kScanWaves, k);
+  for (int p = threadIdx.x; p < k; p += kScanBlock) partial[static_cast<int64_t>(blockIdx.x) * k + p] = res[p];
+}
+
+// Final merge: one workgroup per query.  The running result occupies list
+// slot 0 of the LDS buffer; each round loads up to chunk-1 more lists into
+// the other slots and tree-merges all of them back into slot 0.
+constexpr int kMergeBlock = 1024;
+constexpr int kMergeLdsKeys = 4096;  // per buffer (two buffers: 64 KiB)
+
+__global__ __launch_bounds__(kMergeBlock) void merge_lists_kernel(const uint64_t *__restrict__ partial,
+                                                                  int nlists, int k, int chunk,
+                                                                  int32_t *__restrict__ ids,
+                                                                  int32_t *__restrict__ scores) {
+  __shared__ uint64_t buf[2][kMergeLdsKeys];
+  const int q = blockIdx.x;
+  const uint64_t *lists = partial + static_cast<int64_t>(q) * nlists * k;
+  uint64_t *a = buf[0];
+  uint64_t *b = buf[1];
+  for (int i = threadIdx.x; i < k; i += kMergeBlock) a[i] = 0;
+  for (int l0 = 0; l0 < nlists; l0 += chunk - 1) {
+    const int take = min(chunk - 1, nlists - l0);
+    for (int i = threadIdx.x; i < (chunk - 1) * k; i += kMergeBlock) {
+      const int l = i / k;
+      a[k + i] = (l < take) ? lists[static_cast<int64_t>(l0 + l) * k + (i - l * k)] : 0ull;
+    }
+    uint64_t *res = tree_merge(a, b, chunk, k);
+    if (res != a) {
+      for (int i = threadIdx.x; i < k; i += kMergeBlock) a[i] = res[i];
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < k; i += kMergeBlock) {
+    const uint64_t key = a[i];
+    ids[static_cast<int64_t>(q) * k + i] = key ? key_id(key) : -1;
+    scores[static_cast<int64_t>(q) * k + i] = key ? key_score(key) : 0;
+  }
+}
+
+// Delta of every (query, database vector) pair, for parity checks.
+template <int NC>
+__global__ __launch_bounds__(256) void delta_dump_kernel(const uint4 *__restrict__ tiles, int64_t n,
+                                                         int64_t ntiles, int W,
+                                                         const uint32_t *__restrict__ qcodes,
+                                                         int32_t *__restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int qi = blockIdx.y;
+  if (t >= ntiles) return;
+  QueryWords<NC> q;
+  q.load(qcodes + static_cast<int64_t>(qi) * 2 * W, W);
+  const int32_t delta = tile_delta<NC>(tiles + t * (2 * NC * 64), lane, q);
+  const int64_t id = t * 64 + lane;
+  if (id < n) out[static_cast<int64_t>(qi) * n + id] = delta;
+}
+
+template <int NC, int R>
+hipError_t scan_nc_r(const DbDev &db, const uint32_t *qcode, int k, int grid, uint64_t *partial,
+                     hipStream_t s) {
+  hipLaunchKernelGGL((scan_plain_kernel<NC, R>), dim3(grid), dim3(kScanBlock), 0, s, db.tiles, db.n,
+                     db.ntiles, db.W, qcode, k, partial);
+  return hipGetLastError();
+}
+
+template <int NC>
+hipError_t scan_nc(const DbDev &db, const uint32_t *qcode, int k, int grid, uint64_t *partial,
+                   hipStream_t s) {
+  switch (rows_for_k(k)) {
+    case 1: return scan_nc_r<NC, 1>(db, qcode, k, grid, partial, s);
+    case 2: return scan_nc_r<NC, 2>(db, qcode, k, grid, partial, s);
+    case 4: return scan_nc_r<NC, 4>(db, qcode, k, grid, partial, s);
+    default: return scan_nc_r<NC, 8>(db, qcode, k, grid, partial, s);
+  }
+}
+
+template <int NC>
+hipError_t dump_nc(const DbDev &db, const uint32_t *qcodes, int nq, int32_t *out, hipStream_t s) {
+  const unsigned gx = static_cast<unsigned>((db.ntiles + 3) / 4);
+  hipLaunchKernelGGL((delta_dump_kernel<NC>), dim3(gx, nq), dim3(256), 0, s, db.tiles, db.n, db.ntiles, db.W,
+                     qcodes, out);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t scan_plain_launch(const DbDev &db, const uint32_t *qcode, int k, int grid, uint64_t *partial,
+                             hipStream_t s) {
+  switch (db.nc) {
+    case 1: return scan_nc<1>(db, qcode, k, grid, partial, s);
+    case 2: return scan_nc<2>(db, qcode, k, grid, partial, s);
+    case 3: return scan_nc<3>(db, qcode, k, grid, partial, s);
+    case 4: return scan_nc<4>(db, qcode, k, grid, partial, s);
+    case 5: return scan_nc<5>(db, qcode, k, grid, partial, s);
+    case 6: return scan_nc<6>(db, qcode, k, grid, partial, s);
+    case 7: return scan_nc<7>(db, qcode, k, grid, partial, s);
+    case 8: return scan_nc<8>(db, qcode, k, grid, partial, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t merge_launch(const uint64_t *partial, int nq, int nlists, int k, int32_t *ids, int32_t *scores,
+                        hipStream_t s) {
+  // lists per round: a power of two with chunk * k keys in one LDS buffer
+  int chunk = 2;
+  while (chunk * 2 * k <= kMergeLdsKeys && chunk < 2 * nlists) chunk *= 2;
+  if (chunk * k > kMergeLdsKeys) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(merge_lists_kernel, dim3(nq), dim3(kMergeBlock), 0, s, partial, nlists, k, chunk, ids,
+                     scores);
+  return hipGetLastError();
+}
+
+hipError_t delta_dump_launch(const DbDev &db, const uint32_t *qcodes, int nq, int32_t *out, hipStream_t s) {
+  switch (db.nc) {
+    case 1: return dump_nc<1>(db, qcodes, nq, out, s);
+    case 2: return dump_nc<2>(db, qcodes, nq, out, s);
+    case 3: return dump_nc<3>(db, qcodes, nq, out, s);
+    case 4: return dump_nc<4>(db, qcodes, nq, out, s);
+    case 5: return dump_nc<5>(db, qcodes, nq, out, s);
+    case 6: return dump_nc<6>(db, qcodes, nq, out, s);
+    case 7: return dump_nc<7>(db, qcodes, nq, out, s);
+    case 8: return dump_nc<8>(db, qcodes, nq, out, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace tqi

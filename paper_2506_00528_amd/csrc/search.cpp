@@ -1,0 +1,46 @@
+// search.cpp -- the plain search path: one full database pass per query.
+#include <algorithm>
+
+#include "tq_runtime.h"
+
+namespace tqr {
+
+namespace {
+// Partial lists of one merge round stay under this many bytes of scratch.
+constexpr size_t kPartialBudget = size_t(64) << 20;
+}  // namespace
+
+// Two workgroups of four waves per compute unit keep 16 KiB of loads in flight
+// per wave (d = 1024); never more waves than tiles.
+int default_plain_grid(const tq_db *db) {
+  const int64_t by_tiles = (db->dev.ntiles + 3) / 4;
+  const int64_t by_cu = static_cast<int64_t>(db->num_cu > 0 ? db->num_cu : 256) * 2;
+  return static_cast<int>(std::max<int64_t>(1, std::min(by_tiles, by_cu)));
+}
+
+int search_plain(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids, int32_t *scores, int grid,
+                 hipStream_t s) {
+  const int G = grid > 0 ? grid : default_plain_grid(db);
+  const size_t per_query = static_cast<size_t>(G) * k * sizeof(uint64_t);
+  const int chunk = static_cast<int>(std::max<size_t>(1, std::min<size_t>(nq, kPartialBudget / per_query)));
+  void *p = nullptr;
+  int rc = scratch_get(db->scratch, s, per_query * chunk, &p);
+  if (rc) return rc;
+  uint64_t *partial = static_cast<uint64_t *>(p);
+  const int row_words = 2 * db->dev.W;
+  for (int q0 = 0; q0 < nq; q0 += chunk) {
+    const int nc = std::min(chunk, nq - q0);
+    for (int i = 0; i < nc; ++i) {
+      TimedLaunch t(kTimePlain, s);
+      hipError_t e = tqi::scan_plain_launch(db->dev, qcodes + static_cast<int64_t>(q0 + i) * row_words, k, G,
+                                            partial + static_cast<size_t>(i) * G * k, s);
+      if (e != hipSuccess) return hip_fail(e, "plain scan launch");
+    }
+    hipError_t e = tqi::merge_launch(partial, nc, G, k, ids + static_cast<int64_t>(q0) * k,
+                                     scores + static_cast<int64_t>(q0) * k, s);
+    if (e != hipSuccess) return hip_fail(e, "merge launch");
+  }
+  return TQ_OK;
+}
+
+}  // namespace tqr

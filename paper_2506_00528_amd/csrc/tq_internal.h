@@ -1,0 +1,95 @@
+// tq_internal.h -- internals shared by the HIP kernels and the host runtime of
+// the ternary EVP search library.  Not part of the public ABI (include/tq.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace tqi {
+
+// ---------------------------------------------------------------------------
+// Resident database layout
+// ---------------------------------------------------------------------------
+//
+// The canonical code row (public layout) is [v+ : W words][v- : W words].
+// On the device the database is re-tiled for streaming:
+//
+//   * 64 vectors form a tile, one vector per lane of a wave;
+//   * each plane is padded to W4 = 4*nc words (nc 16-byte chunks);
+//   * the planes are stored as nz = v+ | v- (the non-zero mask) and
+//     ng = v- (the negative mask), a lossless re-coding of (v+, v-) that
+//     lets Delta be evaluated with 5 integer operations per 32 coordinates
+//     (see delta_chunk below);
+//   * within a tile, chunk c of plane p of all 64 vectors is one contiguous
+//     1 KiB run: uint4 index ((tile * 2 + p) * nc + c) * 64 + lane.
+//
+// Rows past n in the last tile are all-zero and are never reported.
+constexpr int kTileVecs = 64;
+constexpr int kMaxNc = 8;  // d <= 1024
+
+struct DbDev {
+  const uint4 *tiles;
+  int64_t n;
+  int64_t ntiles;
+  int d, x, W, nc;
+};
+
+// ---------------------------------------------------------------------------
+// Result keys
+// ---------------------------------------------------------------------------
+//
+// A (score, id) pair is folded into one 64-bit key that orders "nearer" as
+// "larger": high word = Delta + 2^31 (so unsigned order is score order), low
+// word = 0xFFFFFFFF - id (so on equal score the lower id is larger).  The key
+// is a strict total order over a database, so every partial top-k can be
+// merged in any order to the same result.  0 is never a valid key (the high
+// word of a valid key is at least 2^31 - x > 0) and marks an empty slot.
+constexpr uint32_t kScoreBias = 0x80000000u;
+
+__host__ __device__ inline uint64_t make_key(int32_t score, uint32_t id) {
+  return (static_cast<uint64_t>(static_cast<uint32_t>(score) + kScoreBias) << 32) |
+         static_cast<uint64_t>(0xFFFFFFFFu - id);
+}
+__host__ __device__ inline int32_t key_score(uint64_t key) {
+  return static_cast<int32_t>(static_cast<uint32_t>(key >> 32) - kScoreBias);
+}
+__host__ __device__ inline int32_t key_id(uint64_t key) {
+  return static_cast<int32_t>(0xFFFFFFFFu - static_cast<uint32_t>(key));
+}
+
+// Per-wave top-k lists hold 64*R keys (R per lane); R is one of 1, 2, 4, 8.
+inline int rows_for_k(int k) {
+  int r = (k + 63) / 64;
+  return r <= 1 ? 1 : r <= 2 ? 2 : r <= 4 ? 4 : 8;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files); all asynchronous on `s`.
+// ---------------------------------------------------------------------------
+
+// encode.hip
+hipError_t encode_launch(const float *X, int64_t n, int d, int x, uint32_t *codes, int *flags,
+                         int num_cu, hipStream_t s);
+
+// layout.hip
+hipError_t repack_launch(const uint32_t *codes, int64_t n, int d, uint4 *tiles, int64_t ntiles,
+                         int nc, hipStream_t s);
+hipError_t export_launch(const DbDev &db, uint32_t *codes, hipStream_t s);
+hipError_t validate_launch(const uint32_t *codes, int64_t n, int d, int x,
+                           unsigned long long *bad_rows, hipStream_t s);
+
+// scan.hip
+// One query against the whole database; `grid` workgroups, each writing one
+// sorted list of k keys to partial[block * k ...].
+hipError_t scan_plain_launch(const DbDev &db, const uint32_t *qcode, int k, int grid,
+                             uint64_t *partial, hipStream_t s);
+// For each of nq queries, merge its `nlists` sorted lists of k keys (laid out
+// partial[(q * nlists + l) * k + i]) into the final ids / scores.
+hipError_t merge_launch(const uint64_t *partial, int nq, int nlists, int k, int32_t *ids,
+                        int32_t *scores, hipStream_t s);
+hipError_t delta_dump_launch(const DbDev &db, const uint32_t *qcodes, int nq, int32_t *out,
+                             hipStream_t s);
+
+}  // namespace tqi

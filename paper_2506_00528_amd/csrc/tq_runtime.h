@@ -1,0 +1,102 @@
+// tq_runtime.h -- host-side runtime internals of the library (not public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <memory>
+#include <mutex>
+#include <unordered_map>
+
+#include "tq.h"
+#include "tq_internal.h"
+
+namespace tqr {
+
+// --- errors --------------------------------------------------------------
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int hip_fail(hipError_t e, const char *what);
+void clear_error();
+int log_level();
+
+// --- devices ---------------------------------------------------------------
+struct DevCtx {
+  bool ready = false;
+  int num_cu = 0;
+  int *flags = nullptr;  // sticky device error flags (bit 0: non-finite encode input)
+};
+int current_device(int *dev);
+int device_ctx(int dev, DevCtx **out);
+
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int dev);
+  ~DeviceGuard();
+  DeviceGuard(const DeviceGuard &) = delete;
+  DeviceGuard &operator=(const DeviceGuard &) = delete;
+
+ private:
+  int prev_ = -1;
+  bool switched_ = false;
+};
+
+// --- kernel timing ----------------------------------------------------------
+enum TimingFamily { kTimePlain = 0, kTimeBatched = 1 };
+
+// Brackets one kernel launch with HIP events on stream `s` when timing is on.
+class TimedLaunch {
+ public:
+  TimedLaunch(int family, hipStream_t s);
+  ~TimedLaunch();
+  TimedLaunch(const TimedLaunch &) = delete;
+  TimedLaunch &operator=(const TimedLaunch &) = delete;
+
+ private:
+  int family_;
+  hipStream_t s_;
+  hipEvent_t a_ = nullptr, b_ = nullptr;
+};
+
+// --- scratch -----------------------------------------------------------------
+struct Scratch {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+using ScratchMap = std::unordered_map<hipStream_t, Scratch>;
+// Buffer of at least `bytes` private to (owner, stream); growing it waits for
+// the stream first.  The owner's mutex must be held.
+int scratch_get(ScratchMap &map, hipStream_t s, size_t bytes, void **out);
+void scratch_free_all(ScratchMap &map);
+
+int count_bad_codes(const uint32_t *codes, int64_t n, int d, int x, hipStream_t s, unsigned long long *bad);
+
+struct BatchedState;  // batched.cpp
+
+}  // namespace tqr
+
+// The database handle of the public ABI.
+struct tq_db {
+  int device = 0;
+  int num_cu = 0;
+  tqi::DbDev dev{};
+  size_t bytes = 0;
+  std::mutex mu;  // guards scratch and batched state during enqueue
+  tqr::ScratchMap scratch;
+  tqr::BatchedState *batched = nullptr;
+};
+
+namespace tqr {
+
+// search.cpp
+int default_plain_grid(const tq_db *db);
+int search_plain(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids, int32_t *scores, int grid,
+                 hipStream_t s);
+
+// batched.cpp
+int choose_path(tq_db *db, int requested, int nq, int k);
+int search_batched(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids, int32_t *scores,
+                   const tq_search_opts *opts, hipStream_t s);
+void batched_release(tq_db *db);
+
+}  // namespace tqr

@@ -1,0 +1,278 @@
+"""Thin Python binding of the C ABI in include/tq.h (libtq.so).
+
+Argument marshalling only: every step of the search runs in the HIP library.
+Functions keep the C names (``tq_encode``, ``tq_db_create``, ``tq_search_knn``,
+``tq_serve_submit`` ...) and take torch tensors where the C call takes device
+pointers; ``stream`` defaults to torch's current stream on the tensor's device.
+Code tensors are ``torch.int32`` holding the canonical uint32 bit patterns.
+
+The library must have been built (``__graft_entry__.build()`` or
+``python -m paper_2506_00528_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import torch  # imported first so libtq.so binds to the HIP runtime torch loaded
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtq.so")
+
+TQ_OK = 0
+TQ_ERR_INVALID = -1
+TQ_ERR_NOMEM = -2
+TQ_ERR_DEVICE = -3
+TQ_ERR_AGAIN = -4
+TQ_ERR_NOTFOUND = -5
+TQ_ERR_STATE = -6
+
+TQ_PATH_AUTO = 0
+TQ_PATH_PLAIN = 1
+TQ_PATH_BATCHED = 2
+
+TQ_MAX_D = 1024
+TQ_MAX_K = 512
+
+# Every function declared in include/tq.h (checked by the tests).
+EXPORTS = (
+    "tq_status_str", "tq_last_error", "tq_version", "tq_code_words", "tq_encode", "tq_db_create",
+    "tq_db_export", "tq_db_info", "tq_db_destroy", "tq_search_knn", "tq_delta_dump", "tq_sync",
+    "tq_serve_create", "tq_serve_submit", "tq_serve_poll", "tq_serve_wait", "tq_serve_cancel",
+    "tq_serve_stats", "tq_serve_destroy", "tq_timing_enable", "tq_timing_read",
+)
+
+
+class TQError(RuntimeError):
+    def __init__(self, status: int, call: str, detail: str):
+        super().__init__(f"{call}: {status_str(status)}: {detail}")
+        self.status = status
+
+
+class tq_search_opts(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int), ("check_queries", ctypes.c_int), ("grid", ctypes.c_int),
+                ("qtile", ctypes.c_int), ("use_graph", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
+
+
+class tq_serve_cfg(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int), ("max_k", ctypes.c_int),
+                ("n_segments", ctypes.c_int), ("max_request_nq", ctypes.c_int),
+                ("reserved", ctypes.c_int * 4)]
+
+
+class tq_req_stats(ctypes.Structure):
+    _fields_ = [("submit_ns", ctypes.c_uint64), ("admit_ns", ctypes.c_uint64),
+                ("complete_ns", ctypes.c_uint64), ("nq", ctypes.c_int), ("k", ctypes.c_int),
+                ("ticks", ctypes.c_int), ("reserved", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib(path: Optional[str] = None):
+    """The loaded libtq.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"HIP library {p} is not built; run __graft_entry__.build() first")
+    L = ctypes.CDLL(p)
+    vp, i32, i64, u64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t
+    P = ctypes.POINTER
+    sig = {
+        "tq_status_str": ([i32], ctypes.c_char_p),
+        "tq_last_error": ([], ctypes.c_char_p),
+        "tq_version": ([], i32),
+        "tq_code_words": ([i32], i32),
+        "tq_encode": ([vp, i64, i32, i32, vp, vp], i32),
+        "tq_db_create": ([vp, i64, i32, i32, vp, P(vp)], i32),
+        "tq_db_export": ([vp, vp, vp], i32),
+        "tq_db_info": ([vp, P(i64), P(i32), P(i32), P(sz)], i32),
+        "tq_db_destroy": ([vp], i32),
+        "tq_search_knn": ([vp, vp, i32, i32, vp, vp, P(tq_search_opts), vp], i32),
+        "tq_delta_dump": ([vp, vp, i32, vp, vp], i32),
+        "tq_sync": ([vp], i32),
+        "tq_serve_create": ([vp, P(tq_serve_cfg), P(vp)], i32),
+        "tq_serve_submit": ([vp, vp, i32, i32, P(u64)], i32),
+        "tq_serve_poll": ([vp, u64, vp, vp, P(tq_req_stats)], i32),
+        "tq_serve_wait": ([vp, u64, i32, vp, vp, P(tq_req_stats)], i32),
+        "tq_serve_cancel": ([vp, u64], i32),
+        "tq_serve_stats": ([vp, P(u64), P(u64), P(u64), P(u64)], i32),
+        "tq_serve_destroy": ([vp], i32),
+        "tq_timing_enable": ([i32], i32),
+        "tq_timing_read": ([i32, P(ctypes.c_double), P(i64), i32], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    if path is None:
+        _lib = L
+    return L
+
+
+def status_str(status: int) -> str:
+    return lib().tq_status_str(int(status)).decode()
+
+
+def last_error() -> str:
+    return lib().tq_last_error().decode()
+
+
+def _check(rc: int, call: str) -> int:
+    if rc != TQ_OK:
+        raise TQError(rc, call, last_error())
+    return rc
+
+
+def _stream(t: Optional[torch.Tensor], stream) -> int:
+    if stream is not None:
+        return int(stream.cuda_stream if hasattr(stream, "cuda_stream") else stream)
+    dev = t.device if t is not None else torch.device("cuda", torch.cuda.current_device())
+    return int(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _dev(t: torch.Tensor, name: str, dtype: torch.dtype) -> int:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def tq_code_words(d: int) -> int:
+    rc = lib().tq_code_words(int(d))
+    if rc < 0:
+        raise TQError(rc, "tq_code_words", last_error())
+    return rc
+
+
+def tq_encode(X: torch.Tensor, x: int, codes: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Nearest {x,d} EVP vertices of the rows of X (n x d float32, on the GPU),
+    as canonical codes (n x 2W int32 holding uint32 bit patterns)."""
+    if X.dim() != 2:
+        raise ValueError("X must be n x d")
+    n, d = X.shape
+    W = tq_code_words(d)
+    with torch.cuda.device(X.device):
+        if codes is None:
+            codes = torch.empty((n, 2 * W), dtype=torch.int32, device=X.device)
+        if tuple(codes.shape) != (n, 2 * W):
+            raise ValueError("codes has the wrong shape")
+        _check(lib().tq_encode(_dev(X, "X", torch.float32), n, d, int(x), _dev(codes, "codes", torch.int32),
+                               _stream(X, stream)), "tq_encode")
+    return codes
+
+
+def tq_sync(stream=None, device=None) -> None:
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    with torch.cuda.device(dev):
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        _check(lib().tq_sync(_stream(None, s)), "tq_sync")
+
+
+class tq_db:
+    """Owning handle of a resident database (tq_db_create / tq_db_destroy)."""
+
+    def __init__(self, codes: torch.Tensor, d: int, x: int, stream=None):
+        if codes.dim() != 2:
+            raise ValueError("codes must be n x 2W")
+        self.n, self.d, self.x = int(codes.shape[0]), int(d), int(x)
+        self.W = tq_code_words(d)
+        if codes.shape[1] != 2 * self.W:
+            raise ValueError("code width does not match d")
+        self.device = codes.device
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().tq_db_create(_dev(codes, "codes", torch.int32), self.n, self.d, self.x,
+                                      _stream(codes, stream), ctypes.byref(self._h)), "tq_db_create")
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise RuntimeError("database was destroyed")
+        return self._h
+
+    def info(self):
+        n, d, x, b = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int(), ctypes.c_size_t()
+        _check(lib().tq_db_info(self.handle, ctypes.byref(n), ctypes.byref(d), ctypes.byref(x), ctypes.byref(b)),
+               "tq_db_info")
+        return n.value, d.value, x.value, b.value
+
+    def destroy(self):
+        if self._h:
+            with torch.cuda.device(self.device):
+                torch.cuda.synchronize(self.device)
+                _check(lib().tq_db_destroy(self._h), "tq_db_destroy")
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def tq_db_create(codes: torch.Tensor, d: int, x: int, stream=None) -> tq_db:
+    return tq_db(codes, d, x, stream)
+
+
+def tq_db_destroy(db: tq_db) -> None:
+    db.destroy()
+
+
+def tq_db_export(db: tq_db, codes: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    with torch.cuda.device(db.device):
+        if codes is None:
+            codes = torch.empty((db.n, 2 * db.W), dtype=torch.int32, device=db.device)
+        _check(lib().tq_db_export(db.handle, _dev(codes, "codes", torch.int32), _stream(codes, stream)),
+               "tq_db_export")
+    return codes
+
+
+def _opts(path=TQ_PATH_AUTO, check_queries=False, grid=0, qtile=0, use_graph=1):
+    o = tq_search_opts()
+    o.path, o.check_queries, o.grid, o.qtile, o.use_graph = int(path), int(bool(check_queries)), int(grid), \
+        int(qtile), int(use_graph)
+    return o
+
+
+def tq_search_knn(db: tq_db, qcodes: torch.Tensor, k: int, path: int = TQ_PATH_AUTO, check_queries: bool = False,
+                  grid: int = 0, qtile: int = 0, use_graph: int = 1, ids: Optional[torch.Tensor] = None,
+                  scores: Optional[torch.Tensor] = None, stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Top-k (ids, scores) of every query code, nearest first (Delta desc, id asc)."""
+    if qcodes.dim() != 2 or qcodes.shape[1] != 2 * db.W:
+        raise ValueError("qcodes must be nq x 2W for the database's d")
+    nq = int(qcodes.shape[0])
+    with torch.cuda.device(db.device):
+        if ids is None:
+            ids = torch.empty((nq, k), dtype=torch.int32, device=db.device)
+        if scores is None:
+            scores = torch.empty((nq, k), dtype=torch.int32, device=db.device)
+        o = _opts(path, check_queries, grid, qtile, use_graph)
+        _check(lib().tq_search_knn(db.handle, _dev(qcodes, "qcodes", torch.int32), nq, int(k),
+                                   _dev(ids, "ids", torch.int32), _dev(scores, "scores", torch.int32),
+                                   ctypes.byref(o), _stream(qcodes, stream)), "tq_search_knn")
+    return ids, scores
+
+
+def tq_delta_dump(db: tq_db, qcodes: torch.Tensor, stream=None) -> torch.Tensor:
+    nq = int(qcodes.shape[0])
+    with torch.cuda.device(db.device):
+        out = torch.empty((nq, db.n), dtype=torch.int32, device=db.device)
+        _check(lib().tq_delta_dump(db.handle, _dev(qcodes, "qcodes", torch.int32), nq,
+                                   _dev(out, "delta", torch.int32), _stream(qcodes, stream)), "tq_delta_dump")
+    return out
+
+
+def tq_timing_enable(on: bool = True) -> None:
+    _check(lib().tq_timing_enable(int(bool(on))), "tq_timing_enable")
+
+
+def tq_timing_read(which: int = 0, reset: bool = False) -> Tuple[float, int]:
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(lib().tq_timing_read(int(which), ctypes.byref(ms), ctypes.byref(n), int(bool(reset))), "tq_timing_read")
+    return ms.value, n.value

@@ -1,0 +1,247 @@
+"""HIP path against the CPU oracle, element by element (bit-exact: codes,
+Delta and top-k ids/scores are integers).  Every call goes through the C ABI
+(libtq.so via the ctypes binding).  Inputs are seeded; the same float32 bytes
+go to both sides."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from tests.libtq import ensure_built
+from workloads import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stderr.flush()
+
+
+@pytest.fixture(scope="module")
+def tq():
+    return ensure_built()
+
+
+@pytest.fixture(scope="module")
+def o():
+    return oracle.default()
+
+
+def u32(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint32)
+
+
+def gpu_codes(tq, X: np.ndarray, x: int) -> np.ndarray:
+    Xg = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).cuda()
+    codes = tq.tq_encode(Xg, x)
+    tq.tq_sync()
+    return u32(codes)
+
+
+def oracle_codes(o, X, x):
+    return o.pack(o.encode(X, x))
+
+
+def make_db(tq, codes_u32: np.ndarray, d: int, x: int):
+    t = torch.from_numpy(codes_u32.view(np.int32).copy()).cuda()
+    return tq.tq_db_create(t, d, x)
+
+
+def search(tq, db, qcodes_u32, k, **kw):
+    q = torch.from_numpy(qcodes_u32.view(np.int32).copy()).cuda()
+    ids, scores = tq.tq_search_knn(db, q, k, **kw)
+    torch.cuda.synchronize()
+    return ids.cpu().numpy(), scores.cpu().numpy()
+
+
+# ---------------------------------------------------------------------------
+# encode
+# ---------------------------------------------------------------------------
+
+def test_encode_small_workload(tq, o):
+    w = datagen.WORKLOADS["small"]
+    say(f"encode small workload n={w['n']} d={w['d']} x={w['x']}")
+    X = datagen.rows("small", datagen.DB, 0, w["n"]).numpy()
+    Q = datagen.rows("small", datagen.QUERIES, 0, w["nq"]).numpy()
+    for A in (X, Q):
+        g = gpu_codes(tq, A, w["x"])
+        assert np.array_equal(g, oracle_codes(o, A, w["x"]))
+
+
+@pytest.mark.parametrize("d", [1, 2, 31, 32, 33, 63, 64, 65, 100, 127, 128, 129, 383, 384, 385, 500, 512, 640,
+                               767, 768, 769, 1000, 1023, 1024])
+def test_encode_dims(tq, o, d):
+    rng = np.random.default_rng(1000 + d)
+    xs = sorted({1, d, oracle.default_x(d), max(1, d // 4), int(rng.integers(1, d + 1))})
+    n = 67
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    # rows with many equal magnitudes, zeros of both signs and subnormals
+    X[1] = np.round(X[1] * 2) / 2
+    X[2, ::3] = 0.0
+    X[2, 1::3] = -0.0
+    X[3] = np.float32(1e-45) * rng.integers(-3, 4, size=d)
+    X[4] = 0.0
+    X[5] = -0.0
+    for x in xs:
+        say(f"encode d={d} n={n} x={x}")
+        assert np.array_equal(gpu_codes(tq, X, x), oracle_codes(o, X, x)), f"d={d} x={x}"
+
+
+def test_encode_ties(tq, o):
+    rng = np.random.default_rng(5)
+    d = 384
+    X = (rng.integers(-3, 4, size=(300, d)) / 4).astype(np.float32)
+    for x in (1, 7, 96, 200, 383, 384):
+        say(f"encode ties d={d} x={x}")
+        assert np.array_equal(gpu_codes(tq, X, x), oracle_codes(o, X, x))
+
+
+def test_encode_rows_of_many_lengths(tq, o):
+    rng = np.random.default_rng(6)
+    for n in (1, 2, 3, 4, 5, 255, 1025):
+        X = rng.standard_normal((n, 100)).astype(np.float32)
+        say(f"encode n={n} d=100 x=67")
+        assert np.array_equal(gpu_codes(tq, X, 67), oracle_codes(o, X, 67))
+
+
+def test_encode_nonfinite_sets_flag(tq, o):
+    rng = np.random.default_rng(7)
+    X = rng.standard_normal((6, 64)).astype(np.float32)
+    X[2, 5] = np.nan
+    X[4, 63] = np.inf
+    say("encode with NaN / inf rows")
+    Xg = torch.from_numpy(X).cuda()
+    codes = tq.tq_encode(Xg, 16)
+    with pytest.raises(tq.TQError) as e:
+        tq.tq_sync()
+    assert e.value.status == tq.TQ_ERR_INVALID
+    tq.tq_sync()  # the flag was cleared
+    c = u32(codes)
+    assert np.all(c[2] == 0) and np.all(c[4] == 0)
+    good = [0, 1, 3, 5]
+    assert np.array_equal(c[good], oracle_codes(o, X[good], 16))
+
+
+# ---------------------------------------------------------------------------
+# database
+# ---------------------------------------------------------------------------
+
+def test_db_create_rejects_malformed(tq, o):
+    rng = np.random.default_rng(8)
+    d, x = 100, 20
+    C = oracle_codes(o, rng.standard_normal((10, d)).astype(np.float32), x)
+    for what, mutate in (("both planes", lambda c: (c.__setitem__((3, 0), c[3, 0] | np.uint32(1)),
+                                                c.__setitem__((3, 4), c[3, 4] | np.uint32(1)))),
+                         ("padding bit", lambda c: c.__setitem__((5, 3), c[5, 3] | np.uint32(1 << 30))),
+                         ("popcount", lambda c: c.__setitem__((7, 1), c[7, 1] ^ np.uint32(1)))):
+        bad = C.copy()
+        mutate(bad)
+        say(f"db_create rejects: {what}")
+        with pytest.raises(tq.TQError) as e:
+            make_db(tq, bad, d, x)
+        assert e.value.status == tq.TQ_ERR_INVALID
+
+
+@pytest.mark.parametrize("n,d", [(1, 1), (63, 33), (64, 64), (65, 100), (1000, 384), (4099, 1024)])
+def test_db_export_round_trip(tq, o, n, d):
+    rng = np.random.default_rng(9 + n)
+    x = oracle.default_x(d)
+    C = oracle_codes(o, rng.standard_normal((n, d)).astype(np.float32), x)
+    say(f"db export n={n} d={d}")
+    db = make_db(tq, C, d, x)
+    assert db.info()[:3] == (n, d, x)
+    out = tq.tq_db_export(db)
+    torch.cuda.synchronize()
+    assert np.array_equal(u32(out), C)
+    db.destroy()
+
+
+# ---------------------------------------------------------------------------
+# Delta and top-k
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def small(tq, o):
+    w = datagen.WORKLOADS["small"]
+    X = datagen.rows("small", datagen.DB, 0, w["n"]).numpy()
+    Q = datagen.rows("small", datagen.QUERIES, 0, w["nq"]).numpy()
+    V, VQ = o.encode(X, w["x"]), o.encode(Q, w["x"])
+    CX, CQ = o.pack(V), o.pack(VQ)
+    db = make_db(tq, CX, w["d"], w["x"])
+    yield dict(w=w, V=V, VQ=VQ, CX=CX, CQ=CQ, db=db)
+    db.destroy()
+
+
+def test_delta_dump_small_workload(tq, o, small):
+    say("delta dump small workload 100 x 10000")
+    q = torch.from_numpy(small["CQ"].view(np.int32).copy()).cuda()
+    D = tq.tq_delta_dump(small["db"], q)
+    torch.cuda.synchronize()
+    assert np.array_equal(D.cpu().numpy(), o.delta(small["VQ"], small["V"]))
+
+
+@pytest.mark.parametrize("k", [1, 2, 10, 63, 64, 65, 100, 128, 129, 200, 256, 257, 512])
+def test_search_small_workload(tq, o, small, k):
+    say(f"plain search small workload k={k}")
+    ids, sc = search(tq, small["db"], small["CQ"], k, path=tq.TQ_PATH_PLAIN)
+    ei, es = o.knn(small["VQ"], small["V"], k)
+    assert np.array_equal(sc, es)
+    assert np.array_equal(ids, ei)
+
+
+@pytest.mark.parametrize("grid", [1, 2, 3, 7, 40, 100])
+def test_search_grid_shapes(tq, o, small, grid):
+    say(f"plain search small workload grid={grid}")
+    ids, sc = search(tq, small["db"], small["CQ"][:20], 10, path=tq.TQ_PATH_PLAIN, grid=grid)
+    ei, es = o.knn(small["VQ"][:20], small["V"], 10)
+    assert np.array_equal(ids, ei) and np.array_equal(sc, es)
+
+
+@pytest.mark.parametrize("n,d,k", [(1, 16, 1), (2, 33, 2), (63, 64, 63), (64, 100, 64), (65, 100, 65),
+                                   (130, 200, 100), (1007, 384, 300), (4160, 768, 512), (3000, 1024, 17)])
+def test_search_ragged(tq, o, n, d, k):
+    rng = np.random.default_rng(n * 7 + d)
+    x = max(1, d // 3)
+    V = o.encode(rng.standard_normal((n, d)).astype(np.float32), x)
+    VQ = o.encode(rng.standard_normal((5, d)).astype(np.float32), x)
+    say(f"plain search ragged n={n} d={d} x={x} k={k}")
+    db = make_db(tq, o.pack(V), d, x)
+    ids, sc = search(tq, db, o.pack(VQ), k, path=tq.TQ_PATH_PLAIN)
+    ei, es = o.knn(VQ, V, k)
+    assert np.array_equal(sc, es) and np.array_equal(ids, ei)
+    db.destroy()
+
+
+def test_search_heavy_ties(tq, o):
+    """A database of few distinct codes: hundreds of vectors share each score."""
+    rng = np.random.default_rng(21)
+    d, x = 256, 64
+    base = o.encode(rng.standard_normal((6, d)).astype(np.float32), x)
+    V = base[rng.integers(0, 6, size=20000)]
+    VQ = np.concatenate([base[:3], o.encode(rng.standard_normal((3, d)).astype(np.float32), x)])
+    say("plain search heavy ties n=20000 d=256")
+    db = make_db(tq, o.pack(V), d, x)
+    for k in (1, 10, 100, 512):
+        ids, sc = search(tq, db, o.pack(VQ), k, path=tq.TQ_PATH_PLAIN)
+        ei, es = o.knn(VQ, V, k)
+        assert np.array_equal(sc, es) and np.array_equal(ids, ei), k
+    db.destroy()
+
+
+def test_search_rejects_bad_args(tq, o, small):
+    q = torch.from_numpy(small["CQ"][:2].view(np.int32).copy()).cuda()
+    say("search argument checks")
+    for k in (0, tq.TQ_MAX_K + 1):
+        with pytest.raises(tq.TQError):
+            tq.tq_search_knn(small["db"], q, k)
+    bad = small["CQ"][:2].copy()
+    W = bad.shape[1] // 2
+    bad[1, 0] |= np.uint32(1)
+    bad[1, W] |= np.uint32(1)  # coordinate 0 now in both planes
+    qb = torch.from_numpy(bad.view(np.int32).copy()).cuda()
+    with pytest.raises(tq.TQError) as e:
+        tq.tq_search_knn(small["db"], qb, 5, check_queries=True)
+    assert e.value.status == tq.TQ_ERR_INVALID
