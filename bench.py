@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""Benchmark of the ternary EVP search path on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload large|mid|small]
+
+Workload (default "large"): a database of N = 10,000,000 l2-normalised
+d = 1024 float32 embeddings from the seeded 4,096-component anisotropic
+Gaussian mixture, encoded on the GPU to {256,1024} EVP codes (256 bytes per
+vector, 2.56 GB resident), and 10,000 queries of the same mixture; k = 10.
+A step is one batch of 100 queries through the whole query path: tq_encode of
+the float queries, then tq_search_knn on the plain path (one full database
+scan per query, the paper's "exhaustive queries") with top-k; the float
+queries are already resident in HBM when timing starts.
+
+Prints one JSON line: queries/s, the roofline of the scan kernel (algorithmic
+bytes per launch / measured launch time, against 8 TB/s HBM), recall@10
+against an exact FP64 cosine ground truth, and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "queries/sec + HBM GB/s (% peak) at recall@10; p50/p99 latency served vs plain"
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--workload", default="large", choices=["small", "mid", "large"])
+    p.add_argument("--x", type=int, default=0, help="EVP x (default: the workload's)")
+    p.add_argument("--batch", type=int, default=100, help="queries per step")
+    p.add_argument("--path", default="plain", choices=["plain", "batched", "auto"])
+    p.add_argument("--grid", type=int, default=0)
+    p.add_argument("--recall-queries", type=int, default=100)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-sample-rows", type=int, default=1 << 20)
+    p.add_argument("--cpu-sample-queries", type=int, default=160)
+    p.add_argument("--copy-probe", action="store_true",
+                   help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
+    return p.parse_args()
+
+
+def source_sha(*names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2506_00528_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2506_00528_amd import tq
+    from workloads import datagen, metrics
+
+    if not os.path.exists(tq.LIB_PATH):
+        from paper_2506_00528_amd.build import build
+        build()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    wl = datagen.WORKLOADS[args.workload]
+    n, d, k = wl["n"], wl["d"], wl["k"]
+    x = args.x or wl["x"]
+    nq_total = wl["nq"]
+    spec = wl["spec"]
+    W = tq.tq_code_words(d)
+    log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
+
+    # ---- database: generate on the GPU chunk by chunk, encode, ground truth
+    t0 = time.time()
+    queries = datagen.rows(spec, datagen.QUERIES, 0, nq_total, dev)
+    nrec = min(args.recall_queries, nq_total)
+    gt = metrics.ExactTopK(queries[:nrec], 10)
+    codes = torch.empty((n, 2 * W), dtype=torch.int32, device=dev)
+    cpu_rows = min(args.cpu_sample_rows, n) if not args.no_cpu_baseline else 0
+    cpu_X = np.empty((cpu_rows, d), dtype=np.float32) if cpu_rows else None
+    for r0, X in datagen.iter_rows(spec, datagen.DB, 0, n, dev):
+        tq.tq_encode(X, x, codes[r0:r0 + X.shape[0]])
+        gt.add(X, r0)
+        if cpu_rows and r0 < cpu_rows:
+            m = min(X.shape[0], cpu_rows - r0)
+            cpu_X[r0:r0 + m] = X[:m].cpu().numpy()
+    tq.tq_sync()
+    log(f"database generated+encoded: n={n} d={d} x={x} in {time.time() - t0:.1f}s")
+
+    # encode rate of the kernel alone on one resident block
+    blk = datagen.rows(spec, datagen.DB, 0, min(n, 1 << 18), dev)
+    enc_out = torch.empty((blk.shape[0], 2 * W), dtype=torch.int32, device=dev)
+    tq.tq_encode(blk, x, enc_out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        tq.tq_encode(blk, x, enc_out)
+    e1.record()
+    torch.cuda.synchronize()
+    enc_ms = e0.elapsed_time(e1) / 5
+    enc_bytes = blk.numel() * 4 + enc_out.numel() * 4
+    del blk, enc_out
+
+    db = tq.tq_db_create(codes, d, x)
+    del codes
+    torch.cuda.empty_cache()
+    qcodes_all = tq.tq_encode(queries, x)
+    tq.tq_sync()
+
+    path = {"plain": tq.TQ_PATH_PLAIN, "batched": tq.TQ_PATH_BATCHED, "auto": tq.TQ_PATH_AUTO}[args.path]
+
+    # ---- recall on the ground-truth subsample (k=10 and 10@100)
+    ids10, _ = tq.tq_search_knn(db, qcodes_all[:nrec], 10, path=path, grid=args.grid)
+    ids100, _ = tq.tq_search_knn(db, qcodes_all[:nrec], 100, path=path, grid=args.grid)
+    gt_ids, _ = gt.result()
+    recall10 = metrics.recall_at(gt_ids, ids10.cpu().numpy(), 10, 10)
+    recall10_100 = metrics.recall_at(gt_ids, ids100.cpu().numpy(), 10, 100)
+
+    # ---- timed steps
+    B = args.batch
+    out_ids = torch.empty((B, k), dtype=torch.int32, device=dev)
+    out_sc = torch.empty((B, k), dtype=torch.int32, device=dev)
+    qc = torch.empty((B, 2 * W), dtype=torch.int32, device=dev)
+
+    def step(i):
+        q0 = (i * B) % max(1, nq_total - B + 1)
+        tq.tq_encode(queries[q0:q0 + B], x, qc)
+        tq.tq_search_knn(db, qc, k, path=path, grid=args.grid, ids=out_ids, scores=out_sc)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    tq.tq_timing_read(0, reset=True)
+    tq.tq_timing_read(1, reset=True)
+    tq.tq_timing_enable(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        step(args.warmup + i)
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    tq.tq_timing_enable(False)
+    fam = 1 if args.path == "batched" else 0
+    kern_ms, launches = tq.tq_timing_read(fam, reset=True)
+    tq.tq_sync()
+
+    elapsed = t_end - t_start
+    nqueries = args.steps * B
+    qps = nqueries / elapsed
+    ms_per_step = elapsed * 1e3 / args.steps
+    db_bytes = n * 2 * W * 4  # algorithmic bytes of one full scan: both bit planes of every vector
+    avg_launch_ms = kern_ms / launches if launches else float("nan")
+    achieved = db_bytes / (avg_launch_ms * 1e-3) / 1e9 if launches else float("nan")
+
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", "traffic.json")
+    key = f"scan_plain/{args.workload}"
+    if os.path.exists(tf):
+        rec = json.load(open(tf)).get(key)
+        if rec and rec.get("source_sha") == source_sha("scan.hip", "tq_device.h"):
+            traffic = rec.get("hbm_bytes_per_launch")
+
+    result = {
+        "metric": METRIC,
+        "value": round(qps, 2),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: N={n} d={d} x={x} k={k}, {B} queries/step, "
+                               f"{args.path} path (one full database scan per query)",
+                   "n": n, "d": d, "x": x, "k": k, "queries_per_step": B, "path": args.path,
+                   "global_batch": B, "parallelism": "single GPU"},
+        "hbm_gbps": round(achieved, 1),
+        "hbm_frac": round(achieved / HBM_PEAK_GBPS, 4),
+        "recall_at_10": round(recall10, 4),
+        "recall_10_at_100": round(recall10_100, 4),
+        "recall_queries": nrec,
+        "encode": {"rows_per_s": round(enc_bytes / (4 * (d + 2 * W)) / (enc_ms * 1e-3), 1),
+                   "gbps": round(enc_bytes / (enc_ms * 1e-3) / 1e9, 1)},
+        "roofline": {"kernel": "scan_plain_kernel", "bound": "hbm", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": traffic, "bytes_per_launch": db_bytes,
+                     "avg_launch_ms": round(avg_launch_ms, 5), "launches": launches},
+    }
+
+    if args.copy_probe:
+        a = torch.empty(1 << 28, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        result["copy_probe_bytes"] = a.numel() * 4
+
+    # ---- CPU oracle on a bounded sample (rank 0, N=1 only)
+    if cpu_rows:
+        import oracle
+        o = oracle.default()
+        threads = o.num_threads()
+        Vs = o.encode(cpu_X, x)  # set-up: the sample database, encoded once
+        nqs = args.cpu_sample_queries
+        Qs = queries[:nqs].cpu().numpy()
+        t = time.perf_counter()
+        VQ = o.encode(Qs, x)
+        o.knn(VQ, Vs, k)
+        dt = time.perf_counter() - t
+        per_query_full = dt / nqs * (n / cpu_rows)
+        result["cpu_baseline"] = {
+            "value": round(1.0 / per_query_full, 4), "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": f"{nqs} queries encoded + exhaustive top-{k} over the first {cpu_rows} database rows "
+                      f"({dt:.1f}s), scaled by N/{cpu_rows} to the full N={n}"}
+    print(json.dumps(result), flush=True)
+    db.destroy()
+
+
+if __name__ == "__main__":
+    main()
