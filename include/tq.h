@@ -179,6 +179,15 @@ typedef struct tq_search_opts {
 int tq_search_knn(const tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids,
                   int32_t *scores, const tq_search_opts *opts, void *stream);
 
+/* Time the candidate shapes of the batched path (query tile, workgroups) and
+ * the plain path for every batch-size bucket (powers of two up to
+ * min(nq_max, 1024)) and each of the nks values of k in `ks` (host array),
+ * and remember the fastest per (d, k, bucket) for later TQ_PATH_AUTO and
+ * TQ_PATH_BATCHED calls.  If the environment variable TQ_TUNE_CACHE names a
+ * file, the results are also written there and read back by later processes.
+ * Runs searches on `stream` and waits for them. */
+int tq_autotune(const tq_db *db, int nq_max, const int *ks, int nks, void *stream);
+
 /* Debugging / parity aid: the full nq x n matrix of Delta(q_i, s_j)
  * (int32, row-major, device pointer), computed with the same device code as
  * the search.  Asynchronous on `stream`. */

@@ -123,6 +123,8 @@ hipEvent_t pooled_event() {
 }
 }  // namespace
 
+bool timing_enabled() { return g_timing_on.load(std::memory_order_relaxed) != 0; }
+
 TimedLaunch::TimedLaunch(int family, hipStream_t s) : family_(family), s_(s) {
   if (!g_timing_on.load(std::memory_order_relaxed)) return;
   std::lock_guard<std::mutex> g(g_timing.mu);
@@ -372,6 +374,17 @@ int tq_delta_dump(const tq_db *db, const uint32_t *qcodes, int nq, int32_t *delt
   hipError_t e = tqi::delta_dump_launch(db->dev, qcodes, nq, delta, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "delta dump launch");
   return TQ_OK;
+}
+
+int tq_autotune(const tq_db *cdb, int nq_max, const int *ks, int nks, void *stream) {
+  clear_error();
+  tq_db *db = const_cast<tq_db *>(cdb);
+  if (!db) return fail(TQ_ERR_INVALID, "null db");
+  if (nq_max < 1) return fail(TQ_ERR_INVALID, "nq_max=%d < 1", nq_max);
+  if (!ks || nks < 1) return fail(TQ_ERR_INVALID, "no k values");
+  DeviceGuard g(db->device);
+  std::lock_guard<std::mutex> l(db->mu);
+  return autotune(db, nq_max, ks, nks, static_cast<hipStream_t>(stream), log_level() >= 2);
 }
 
 int tq_timing_enable(int enable) {

@@ -1,22 +1,411 @@
-// batched.cpp -- the batched search path (placeholder until its kernel lands).
+// batched.cpp -- host runtime of the batched search path: per-bucket device
+// resources and hipGraphs, the shape autotuner and its cache, and the choice
+// between the plain and the batched path.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "tq_batched.h"
 #include "tq_runtime.h"
 
 namespace tqr {
 
-struct BatchedState {};
+namespace {
 
-int choose_path(tq_db *, int requested, int, int) {
-  return requested == TQ_PATH_BATCHED ? TQ_PATH_BATCHED : TQ_PATH_PLAIN;
+constexpr int kMaxBucket = 1024;
+
+int bucket_of(int nq) {
+  int b = 1;
+  while (b < nq) b <<= 1;
+  return b;
 }
 
-int search_batched(tq_db *, const uint32_t *, int, int, int32_t *, int32_t *, const tq_search_opts *,
-                   hipStream_t) {
-  return fail(TQ_ERR_STATE, "the batched path is not available in this build");
+struct Shape {
+  int qtile = 0;
+  int grid = 0;
+  bool plain = false;  // the plain path was faster for this bucket
+};
+
+// ---------------------------------------------------------------------------
+// tuning cache: key "nc<nc>/r<R>/b<bucket>" -> Shape; optional JSON file
+// ---------------------------------------------------------------------------
+struct TuneCache {
+  std::mutex mu;
+  bool loaded = false;
+  std::map<std::string, Shape> map;
+};
+TuneCache g_tune;
+
+std::string tune_key(int nc, int k, int bucket) {
+  char b[64];
+  std::snprintf(b, sizeof b, "nc%d/r%d/b%d", nc, tqi::rows_for_k(k), bucket);
+  return b;
+}
+
+const char *tune_file() { return std::getenv("TQ_TUNE_CACHE"); }
+
+void tune_load_locked() {
+  if (g_tune.loaded) return;
+  g_tune.loaded = true;
+  const char *f = tune_file();
+  if (!f) return;
+  FILE *fp = std::fopen(f, "r");
+  if (!fp) return;
+  char line[256];
+  while (std::fgets(line, sizeof line, fp)) {
+    char key[64];
+    Shape s;
+    int plain = 0;
+    if (std::sscanf(line, " \"%63[^\"]\": {\"qtile\": %d, \"grid\": %d, \"plain\": %d}", key, &s.qtile, &s.grid,
+                    &plain) == 4) {
+      s.plain = plain != 0;
+      g_tune.map[key] = s;
+    }
+  }
+  std::fclose(fp);
+}
+
+void tune_save_locked() {
+  const char *f = tune_file();
+  if (!f) return;
+  std::string tmp = std::string(f) + ".tmp";
+  FILE *fp = std::fopen(tmp.c_str(), "w");
+  if (!fp) return;
+  std::fprintf(fp, "{\n");
+  size_t i = 0;
+  for (auto &kv : g_tune.map) {
+    std::fprintf(fp, " \"%s\": {\"qtile\": %d, \"grid\": %d, \"plain\": %d}%s\n", kv.first.c_str(), kv.second.qtile,
+                 kv.second.grid, kv.second.plain ? 1 : 0, ++i < g_tune.map.size() ? "," : "");
+  }
+  std::fprintf(fp, "}\n");
+  std::fclose(fp);
+  std::rename(tmp.c_str(), f);
+}
+
+bool tune_lookup(int nc, int k, int bucket, Shape *out) {
+  std::lock_guard<std::mutex> g(g_tune.mu);
+  tune_load_locked();
+  auto it = g_tune.map.find(tune_key(nc, k, bucket));
+  if (it == g_tune.map.end()) return false;
+  *out = it->second;
+  return true;
+}
+
+void tune_store(int nc, int k, int bucket, const Shape &s) {
+  std::lock_guard<std::mutex> g(g_tune.mu);
+  tune_load_locked();
+  g_tune.map[tune_key(nc, k, bucket)] = s;
+  tune_save_locked();
+}
+
+Shape default_shape(const tq_db *db, int k, int bucket) {
+  Shape s;
+  const int qmax = tqi::batched_max_qtile(k);
+  s.qtile = std::min(qmax, bucket <= 2 ? 2 : bucket <= 4 ? 4 : bucket <= 8 ? 8 : 16);
+  s.grid = (db->num_cu > 0 ? db->num_cu : 256) * 2;
+  s.plain = bucket == 1;
+  return s;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// per-database state: buffers and graphs per (stream, bucket, k, shape)
+// ---------------------------------------------------------------------------
+
+struct BatchEntry {
+  uint32_t *qprep = nullptr;
+  tqi::BatchParams *prm = nullptr;
+  uint64_t *partial = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+struct BatchedState {
+  hipStream_t capture = nullptr;
+  std::map<std::tuple<hipStream_t, int, int, int, int>, BatchEntry> entries;
+};
+
+namespace {
+
+void free_entry(BatchEntry &e) {
+  if (e.exec) (void)hipGraphExecDestroy(e.exec);
+  if (e.graph) (void)hipGraphDestroy(e.graph);
+  if (e.qprep) (void)hipFree(e.qprep);
+  if (e.prm) (void)hipFree(e.prm);
+  if (e.partial) (void)hipFree(e.partial);
+  e = BatchEntry{};
+}
+
+int get_entry(tq_db *db, hipStream_t s, int bucket, int k, const Shape &sh, BatchEntry **out) {
+  if (!db->batched) db->batched = new BatchedState();
+  BatchedState &st = *db->batched;
+  auto key = std::make_tuple(s, bucket, k, sh.qtile, sh.grid);
+  auto it = st.entries.find(key);
+  if (it != st.entries.end()) {
+    *out = &it->second;
+    return TQ_OK;
+  }
+  BatchEntry e;
+  const size_t qbytes = static_cast<size_t>(bucket) * 8 * db->dev.nc * sizeof(uint32_t);
+  const size_t lists = static_cast<size_t>(sh.qtile) * sh.grid + bucket;
+  hipError_t err = hipMalloc(&e.qprep, qbytes);
+  if (err == hipSuccess) err = hipMalloc(&e.prm, sizeof(tqi::BatchParams));
+  if (err == hipSuccess) err = hipMalloc(&e.partial, lists * k * sizeof(uint64_t));
+  if (err != hipSuccess) {
+    free_entry(e);
+    return hip_fail(err, "hipMalloc(batched buffers)");
+  }
+  *out = &(st.entries[key] = e);
+  return TQ_OK;
+}
+
+int enqueue_scan_merge(tq_db *db, BatchEntry &e, int bucket, int k, const Shape &sh, hipStream_t s) {
+  hipError_t err = tqi::scan_batched_launch(db->dev, e.qprep, e.prm, k, sh.qtile, sh.grid, e.partial, s);
+  if (err != hipSuccess) return hip_fail(err, "batched scan launch");
+  err = tqi::merge_batched_launch(e.partial, e.prm, bucket, k, s);
+  if (err != hipSuccess) return hip_fail(err, "batched merge launch");
+  return TQ_OK;
+}
+
+int ensure_graph(tq_db *db, BatchEntry &e, int bucket, int k, const Shape &sh) {
+  if (e.exec) return TQ_OK;
+  BatchedState &st = *db->batched;
+  hipError_t err = hipSuccess;
+  if (!st.capture) {
+    err = hipStreamCreateWithFlags(&st.capture, hipStreamNonBlocking);
+    if (err != hipSuccess) return hip_fail(err, "hipStreamCreate(capture)");
+  }
+  err = hipStreamBeginCapture(st.capture, hipStreamCaptureModeThreadLocal);
+  if (err != hipSuccess) return hip_fail(err, "hipStreamBeginCapture");
+  int rc = enqueue_scan_merge(db, e, bucket, k, sh, st.capture);
+  hipGraph_t g = nullptr;
+  err = hipStreamEndCapture(st.capture, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (err != hipSuccess) return hip_fail(err, "hipStreamEndCapture");
+  hipGraphExec_t x = nullptr;
+  err = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (err != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return hip_fail(err, "hipGraphInstantiate");
+  }
+  e.graph = g;
+  e.exec = x;
+  return TQ_OK;
+}
+
+// One chunk of <= kMaxBucket queries.
+int run_chunk(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids, int32_t *scores, const Shape &sh,
+              bool use_graph, hipStream_t s) {
+  const int bucket = bucket_of(nq);
+  BatchEntry *e = nullptr;
+  int rc = get_entry(db, s, bucket, k, sh, &e);
+  if (rc) return rc;
+  hipError_t err = tqi::batch_prep_launch(qcodes, nq, bucket, db->dev, sh.qtile, sh.grid, ids, scores, e->qprep,
+                                          e->prm, s);
+  if (err != hipSuccess) return hip_fail(err, "batch prep launch");
+  if (timing_enabled()) {
+    // timed runs launch directly so the events bracket the scan kernel alone
+    {
+      TimedLaunch t(kTimeBatched, s);
+      err = tqi::scan_batched_launch(db->dev, e->qprep, e->prm, k, sh.qtile, sh.grid, e->partial, s);
+    }
+    if (err != hipSuccess) return hip_fail(err, "batched scan launch");
+    err = tqi::merge_batched_launch(e->partial, e->prm, bucket, k, s);
+    if (err != hipSuccess) return hip_fail(err, "batched merge launch");
+    return TQ_OK;
+  }
+  if (use_graph) {
+    if ((rc = ensure_graph(db, *e, bucket, k, sh))) return rc;
+    err = hipGraphLaunch(e->exec, s);
+    if (err != hipSuccess) return hip_fail(err, "hipGraphLaunch");
+    return TQ_OK;
+  }
+  return enqueue_scan_merge(db, *e, bucket, k, sh, s);
+}
+
+Shape shape_for(tq_db *db, int k, int bucket, const tq_search_opts *opts) {
+  Shape sh;
+  if (!tune_lookup(db->dev.nc, k, bucket, &sh)) sh = default_shape(db, k, bucket);
+  if (opts && opts->qtile > 0) sh.qtile = opts->qtile;
+  if (opts && opts->grid > 0) sh.grid = opts->grid;
+  return sh;
+}
+
+}  // namespace
+
+int choose_path(tq_db *db, int requested, int nq, int k) {
+  if (requested != TQ_PATH_AUTO) return requested;
+  const int bucket = bucket_of(std::min(nq, kMaxBucket));
+  Shape sh;
+  if (!tune_lookup(db->dev.nc, k, bucket, &sh)) sh = default_shape(db, k, bucket);
+  return sh.plain ? TQ_PATH_PLAIN : TQ_PATH_BATCHED;
+}
+
+int search_batched(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids, int32_t *scores,
+                   const tq_search_opts *opts, hipStream_t s) {
+  const bool use_graph = opts ? opts->use_graph != 0 : true;
+  if (opts && opts->qtile > 0) {
+    const int q = opts->qtile;
+    if (q != 2 && q != 4 && q != 8 && q != 16) return fail(TQ_ERR_INVALID, "qtile=%d is not 2, 4, 8 or 16", q);
+    if (q > tqi::batched_max_qtile(k))
+      return fail(TQ_ERR_INVALID, "qtile=%d exceeds %d for k=%d", q, tqi::batched_max_qtile(k), k);
+  }
+  const int row_words = 2 * db->dev.W;
+  for (int q0 = 0; q0 < nq; q0 += kMaxBucket) {
+    const int m = std::min(kMaxBucket, nq - q0);
+    const Shape sh = shape_for(db, k, bucket_of(m), opts);
+    int rc = run_chunk(db, qcodes + static_cast<int64_t>(q0) * row_words, m, k, ids + static_cast<int64_t>(q0) * k,
+                       scores + static_cast<int64_t>(q0) * k, sh, use_graph, s);
+    if (rc) return rc;
+  }
+  return TQ_OK;
 }
 
 void batched_release(tq_db *db) {
+  if (!db->batched) return;
+  for (auto &kv : db->batched->entries) free_entry(kv.second);
+  if (db->batched->capture) (void)hipStreamDestroy(db->batched->capture);
   delete db->batched;
   db->batched = nullptr;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+
+// Times `reps` runs of one configuration (plain path when sh.plain) on `s`.
+static int time_config(tq_db *db, const uint32_t *q, int nq, int k, int32_t *ids, int32_t *scores, const Shape &sh,
+                       hipStream_t s, float *ms_out) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+    return fail(TQ_ERR_DEVICE, "hipEventCreate");
+  int rc = TQ_OK;
+  float best = 1e30f;
+  for (int rep = 0; rep < 3 && rc == TQ_OK; ++rep) {
+    (void)hipEventRecord(a, s);
+    if (sh.plain)
+      rc = search_plain(db, q, nq, k, ids, scores, 0, s);
+    else
+      rc = run_chunk(db, q, nq, k, ids, scores, sh, true, s);
+    (void)hipEventRecord(b, s);
+    if (hipEventSynchronize(b) != hipSuccess) rc = fail(TQ_ERR_DEVICE, "hipEventSynchronize");
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    if (rep > 0) best = std::min(best, ms);  // the first run builds graphs and buffers
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  *ms_out = best;
+  return rc;
+}
+
+int autotune_view(tq_db *db, int nq_max, const int *ks, int nks, hipStream_t s, int verbose);
+
+// Shapes are timed on the first kTunePrefix vectors of the database (a full
+// pass of a large database per candidate would make tuning slow); graphs and
+// buffers built on that prefix view are dropped afterwards.
+constexpr int64_t kTunePrefix = int64_t(1) << 21;
+
+int autotune(tq_db *db, int nq_max, const int *ks, int nks, hipStream_t s, int verbose) {
+  const tqi::DbDev full = db->dev;
+  batched_release(db);
+  if (db->dev.n > kTunePrefix) {
+    db->dev.n = kTunePrefix;
+    db->dev.ntiles = kTunePrefix / tqi::kTileVecs;
+  }
+  int rc = autotune_view(db, nq_max, ks, nks, s, verbose);
+  (void)hipStreamSynchronize(s);
+  batched_release(db);
+  db->dev = full;
+  return rc;
+}
+
+int autotune_view(tq_db *db, int nq_max, const int *ks, int nks, hipStream_t s, int verbose) {
+  const int maxb = bucket_of(std::min(std::max(nq_max, 1), kMaxBucket));
+  // queries: copies of the first database rows (valid codes of the right (d, x))
+  const int nqq = std::min<int64_t>(maxb, db->dev.n);
+  uint32_t *q = nullptr;
+  int32_t *ids = nullptr, *scores = nullptr;
+  const int W = db->dev.W;
+  hipError_t err = hipMalloc(&q, static_cast<size_t>(maxb) * 2 * W * sizeof(uint32_t));
+  int kmax = 1;
+  for (int i = 0; i < nks; ++i) kmax = std::max(kmax, ks[i]);
+  if (err == hipSuccess) err = hipMalloc(&ids, static_cast<size_t>(maxb) * kmax * sizeof(int32_t));
+  if (err == hipSuccess) err = hipMalloc(&scores, static_cast<size_t>(maxb) * kmax * sizeof(int32_t));
+  tqi::DbDev head = db->dev;
+  head.n = nqq;
+  head.ntiles = (nqq + 63) / 64;
+  if (err == hipSuccess) err = tqi::export_launch(head, q, s);
+  for (int r = nqq; err == hipSuccess && r < maxb; r += nqq) {
+    const int m = std::min(nqq, maxb - r);
+    err = hipMemcpyAsync(q + static_cast<size_t>(r) * 2 * W, q, static_cast<size_t>(m) * 2 * W * sizeof(uint32_t),
+                         hipMemcpyDeviceToDevice, s);
+  }
+  if (err == hipSuccess) err = hipStreamSynchronize(s);
+  int rc = err == hipSuccess ? TQ_OK : hip_fail(err, "autotune set-up");
+  const int cu = db->num_cu > 0 ? db->num_cu : 256;
+  for (int ki = 0; ki < nks && rc == TQ_OK; ++ki) {
+    const int k = ks[ki];
+    if (k < 1 || k > TQ_MAX_K || k > db->dev.n) {
+      rc = fail(TQ_ERR_INVALID, "autotune: k=%d outside [1, min(n, %d)]", k, TQ_MAX_K);
+      break;
+    }
+    for (int b = 1; b <= maxb && rc == TQ_OK; b <<= 1) {
+      std::vector<Shape> cands;
+      Shape p;
+      p.plain = true;
+      if (b <= 16) cands.push_back(p);
+      for (int qt : {2, 4, 8, 16}) {
+        if (qt > tqi::batched_max_qtile(k) || qt > 2 * b) continue;
+        if (qt < 4 && b > 8) continue;
+        for (int gm : {1, 2, 4}) {
+          Shape c;
+          c.qtile = qt;
+          c.grid = cu * gm;
+          cands.push_back(c);
+        }
+      }
+      Shape best;
+      float best_ms = 1e30f;
+      for (const Shape &c : cands) {
+        float ms = 0.f;
+        rc = time_config(db, q, b, k, ids, scores, c, s, &ms);
+        if (rc) break;
+        if (verbose)
+          std::fprintf(stderr, "[tq tune] k=%d bucket=%d %s qtile=%d grid=%d: %.3f ms\n", k, b,
+                       c.plain ? "plain" : "batched", c.qtile, c.grid, ms);
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = c;
+        }
+      }
+      if (rc == TQ_OK) {
+        if (best.plain) {  // keep a batched shape for explicit batched calls
+          Shape d = default_shape(db, k, b);
+          best.qtile = d.qtile;
+          best.grid = d.grid;
+        }
+        tune_store(db->dev.nc, k, b, best);
+      }
+    }
+  }
+  (void)hipStreamSynchronize(s);
+  if (q) (void)hipFree(q);
+  if (ids) (void)hipFree(ids);
+  if (scores) (void)hipFree(scores);
+  return rc;
 }
 
 }  // namespace tqr

@@ -1,0 +1,202 @@
+// batched_kernels.hip -- all queries of a batch share each database pass.
+//
+// A persistent grid walks work items (query tile, database part); item i is
+// tile (i mod nqt) of part (i div nqt), so consecutive workgroups read the
+// same database part at the same time and share it through L2.  The four
+// waves of a workgroup split the part's 64-vector tiles; a lane keeps its
+// tile vector's two planes in VGPRs and scores it against every query of the
+// tile, reading the query words through the scalar unit.  Each wave keeps one
+// register top-k list per query; at the end of an item the four wave lists of
+// each query are tree-merged in LDS and written as that (query, part) list.
+//
+// Per-call values (query count, derived split) sit in a small device block
+// written by batch_prep_kernel, so the scan and merge launches have fixed
+// arguments and can be captured once in a hipGraph per batch-size bucket and
+// replayed.  Query tiles past the real query count are skipped, never scored.
+#include "tq_batched.h"
+#include "tq_device.h"
+
+namespace tqi {
+namespace {
+
+constexpr int kBatchWaves = 4;
+constexpr int kBatchBlock = 64 * kBatchWaves;
+
+// Canonical query codes -> nz/ng words padded to 4*nc per plane (the layout
+// the scan reads); writes the call's parameters.  Threads past the real
+// queries write zeros for the bucket's padding rows.
+__global__ __launch_bounds__(256) void batch_prep_kernel(const uint32_t *__restrict__ qcodes, int nq, int bucket,
+                                                         int W, int nc, int qtile, int grid, int64_t ntiles,
+                                                         int32_t *ids, int32_t *scores, uint32_t *__restrict__ qprep,
+                                                         BatchParams *__restrict__ prm) {
+  const int W4 = 4 * nc;
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g < static_cast<int64_t>(bucket) * W4) {
+    const int q = static_cast<int>(g / W4);
+    const int w = static_cast<int>(g - static_cast<int64_t>(q) * W4);
+    uint32_t p = 0, m = 0;
+    if (q < nq && w < W) {
+      p = qcodes[static_cast<int64_t>(q) * 2 * W + w];
+      m = qcodes[static_cast<int64_t>(q) * 2 * W + W + w];
+    }
+    qprep[static_cast<int64_t>(q) * 2 * W4 + w] = p | m;
+    qprep[static_cast<int64_t>(q) * 2 * W4 + W4 + w] = m;
+  }
+  if (g == 0) {
+    BatchParams b;
+    b.nq = nq;
+    b.nqt = (nq + qtile - 1) / qtile;
+    int64_t parts = (grid + b.nqt - 1) / b.nqt;
+    if (parts > ntiles) parts = ntiles;
+    if (parts < 1) parts = 1;
+    b.parts = static_cast<int>(parts);
+    b.tiles_per_part = (ntiles + parts - 1) / parts;
+    b.ids = ids;
+    b.scores = scores;
+    *prm = b;
+  }
+}
+
+template <int NC, int R, int QT>
+__global__ __launch_bounds__(kBatchBlock) void scan_batched_kernel(const uint4 *__restrict__ tiles, int64_t n,
+                                                                  int64_t ntiles,
+                                                                  const uint32_t *__restrict__ qprep,
+                                                                  const BatchParams *__restrict__ prm, int k,
+                                                                  uint64_t *__restrict__ partial) {
+  __shared__ uint64_t lds[2][kBatchWaves * 64 * R];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int nq = prm->nq, nqt = prm->nqt, parts = prm->parts;
+  const int64_t tpp = prm->tiles_per_part;
+  const int items = nqt * parts;
+  const int km1 = k - 1;
+
+  for (int item = blockIdx.x; item < items; item += gridDim.x) {
+    const int qt = item % nqt;
+    const int part = item / nqt;
+    const int q0 = qt * QT;
+    const int nact = min(QT, nq - q0);
+    const int64_t t0 = static_cast<int64_t>(part) * tpp;
+    const int64_t t1 = min(ntiles, t0 + tpp);
+
+    WaveList<R> list[QT];
+    uint64_t thr[QT];
+#pragma unroll
+    for (int qi = 0; qi < QT; ++qi) {
+      list[qi].clear();
+      thr[qi] = 0;
+    }
+
+    for (int64_t t = t0 + wave; t < t1; t += kBatchWaves) {
+      const uint4 *tp = tiles + t * (2 * NC * 64);
+      u32x4 vz[NC], vg[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        vz[c] = load_stream(tp + c * 64 + lane);
+        vg[c] = load_stream(tp + (NC + c) * 64 + lane);
+      }
+      const int64_t id = t * 64 + lane;
+      const bool ok = id < n;
+#pragma unroll
+      for (int qi = 0; qi < QT; ++qi) {
+        if (qi < nact) {
+          const uint32_t *qw = qprep + static_cast<int64_t>(q0 + qi) * (8 * NC);
+          DeltaAcc a;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            delta_word(a, qw[4 * c + 0], qw[4 * NC + 4 * c + 0], vz[c].x, vg[c].x);
+            delta_word(a, qw[4 * c + 1], qw[4 * NC + 4 * c + 1], vz[c].y, vg[c].y);
+            delta_word(a, qw[4 * c + 2], qw[4 * NC + 4 * c + 2], vz[c].z, vg[c].z);
+            delta_word(a, qw[4 * c + 3], qw[4 * NC + 4 * c + 3], vz[c].w, vg[c].w);
+          }
+          const uint64_t key = make_key(delta_value(a), static_cast<uint32_t>(id));
+          offer_keys<R>(list[qi], thr[qi], key, ok, km1, lane);
+        }
+      }
+    }
+
+    // merge the four wave lists of each active query of the tile
+#pragma unroll
+    for (int qi = 0; qi < QT; ++qi) {
+      if (qi < nact) {
+        uint64_t *a = lds[0];
+        uint64_t *b = lds[1];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int p = r * 64 + lane;
+          if (p < k) a[wave * k + p] = list[qi].v[r];
+        }
+        uint64_t *res = tree_merge(a, b, kBatchWaves, k);
+        uint64_t *dst = partial + (static_cast<int64_t>(q0 + qi) * parts + part) * k;
+        for (int p = threadIdx.x; p < k; p += kBatchBlock) dst[p] = res[p];
+        __syncthreads();
+      }
+    }
+  }
+}
+
+template <int NC, int R, int QT>
+hipError_t launch3(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int grid,
+                   uint64_t *partial, hipStream_t s) {
+  hipLaunchKernelGGL((scan_batched_kernel<NC, R, QT>), dim3(grid), dim3(kBatchBlock), 0, s, db.tiles, db.n,
+                     db.ntiles, qprep, prm, k, partial);
+  return hipGetLastError();
+}
+
+template <int NC, int R, int QMAX>
+hipError_t launch2(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile, int grid,
+                   uint64_t *partial, hipStream_t s) {
+  if (qtile > QMAX) return hipErrorInvalidValue;
+  switch (qtile) {
+    case 2: return launch3<NC, R, 2>(db, qprep, prm, k, grid, partial, s);
+    case 4: return launch3<NC, R, 4>(db, qprep, prm, k, grid, partial, s);
+    case 8: return launch3<NC, R, (QMAX >= 8 ? 8 : 4)>(db, qprep, prm, k, grid, partial, s);
+    case 16: return launch3<NC, R, (QMAX >= 16 ? 16 : 4)>(db, qprep, prm, k, grid, partial, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int NC>
+hipError_t launch1(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile, int grid,
+                   uint64_t *partial, hipStream_t s) {
+  switch (rows_for_k(k)) {
+    case 1: return launch2<NC, 1, 16>(db, qprep, prm, k, qtile, grid, partial, s);
+    case 2: return launch2<NC, 2, 16>(db, qprep, prm, k, qtile, grid, partial, s);
+    case 4: return launch2<NC, 4, 8>(db, qprep, prm, k, qtile, grid, partial, s);
+    default: return launch2<NC, 8, 4>(db, qprep, prm, k, qtile, grid, partial, s);
+  }
+}
+
+}  // namespace
+
+int batched_max_qtile(int k) {
+  const int r = rows_for_k(k);
+  return r <= 2 ? 16 : r == 4 ? 8 : 4;
+}
+
+hipError_t batch_prep_launch(const uint32_t *qcodes, int nq, int bucket, const DbDev &db, int qtile, int grid,
+                             int32_t *ids, int32_t *scores, uint32_t *qprep, BatchParams *prm, hipStream_t s) {
+  const int64_t threads = static_cast<int64_t>(bucket) * 4 * db.nc;
+  const unsigned blocks = static_cast<unsigned>((threads + 255) / 256);
+  hipLaunchKernelGGL(batch_prep_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, qcodes, nq, bucket, db.W,
+                     db.nc, qtile, grid, db.ntiles, ids, scores, qprep, prm);
+  return hipGetLastError();
+}
+
+hipError_t scan_batched_launch(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile,
+                               int grid, uint64_t *partial, hipStream_t s) {
+  if (qtile > batched_max_qtile(k)) return hipErrorInvalidValue;
+  switch (db.nc) {
+    case 1: return launch1<1>(db, qprep, prm, k, qtile, grid, partial, s);
+    case 2: return launch1<2>(db, qprep, prm, k, qtile, grid, partial, s);
+    case 3: return launch1<3>(db, qprep, prm, k, qtile, grid, partial, s);
+    case 4: return launch1<4>(db, qprep, prm, k, qtile, grid, partial, s);
+    case 5: return launch1<5>(db, qprep, prm, k, qtile, grid, partial, s);
+    case 6: return launch1<6>(db, qprep, prm, k, qtile, grid, partial, s);
+    case 7: return launch1<7>(db, qprep, prm, k, qtile, grid, partial, s);
+    case 8: return launch1<8>(db, qprep, prm, k, qtile, grid, partial, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace tqi

@@ -10,6 +10,7 @@
 // offers keys above its current k-th key, so insertions are rare.  At the end
 // the workgroup's wave lists are tree-merged in LDS and written out; a second
 // kernel merges the workgroup lists of every query into ids and scores.
+#include "tq_batched.h"
 #include "tq_device.h"
 
 namespace tqi {
@@ -61,12 +62,21 @@ __global__ __launch_bounds__(kScanBlock) void scan_plain_kernel(const uint4 *__r
 constexpr int kMergeBlock = 1024;
 constexpr int kMergeLdsKeys = 4096;  // per buffer (two buffers: 64 KiB)
 
+// With `prm` set (batched path) the query count, list count and outputs come
+// from the device parameter block and workgroups past the real queries exit.
 __global__ __launch_bounds__(kMergeBlock) void merge_lists_kernel(const uint64_t *__restrict__ partial,
                                                                   int nlists, int k, int chunk,
                                                                   int32_t *__restrict__ ids,
-                                                                  int32_t *__restrict__ scores) {
+                                                                  int32_t *__restrict__ scores,
+                                                                  const BatchParams *__restrict__ prm) {
   __shared__ uint64_t buf[2][kMergeLdsKeys];
   const int q = blockIdx.x;
+  if (prm) {
+    if (q >= prm->nq) return;
+    nlists = prm->parts;
+    ids = prm->ids;
+    scores = prm->scores;
+  }
   const uint64_t *lists = partial + static_cast<int64_t>(q) * nlists * k;
   uint64_t *a = buf[0];
   uint64_t *b = buf[1];
@@ -151,14 +161,28 @@ hipError_t scan_plain_launch(const DbDev &db, const uint32_t *qcode, int k, int 
   }
 }
 
+// Lists per merge round: a power of two with chunk * k keys in one LDS buffer.
+static int merge_chunk(int k, int nlists) {
+  int chunk = 2;
+  while (chunk * 2 * k <= kMergeLdsKeys && chunk < 2 * nlists && chunk < 512) chunk *= 2;
+  return chunk;
+}
+
 hipError_t merge_launch(const uint64_t *partial, int nq, int nlists, int k, int32_t *ids, int32_t *scores,
                         hipStream_t s) {
-  // lists per round: a power of two with chunk * k keys in one LDS buffer
-  int chunk = 2;
-  while (chunk * 2 * k <= kMergeLdsKeys && chunk < 2 * nlists) chunk *= 2;
+  const int chunk = merge_chunk(k, nlists);
   if (chunk * k > kMergeLdsKeys) return hipErrorInvalidValue;
   hipLaunchKernelGGL(merge_lists_kernel, dim3(nq), dim3(kMergeBlock), 0, s, partial, nlists, k, chunk, ids,
-                     scores);
+                     scores, static_cast<const BatchParams *>(nullptr));
+  return hipGetLastError();
+}
+
+hipError_t merge_batched_launch(const uint64_t *partial, const BatchParams *prm, int bucket, int k,
+                                hipStream_t s) {
+  const int chunk = merge_chunk(k, 1 << 20);
+  if (chunk * k > kMergeLdsKeys) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(merge_lists_kernel, dim3(bucket), dim3(kMergeBlock), 0, s, partial, 0, k, chunk,
+                     static_cast<int32_t *>(nullptr), static_cast<int32_t *>(nullptr), prm);
   return hipGetLastError();
 }
 

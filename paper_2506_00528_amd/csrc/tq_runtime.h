@@ -44,6 +44,8 @@ class DeviceGuard {
 // --- kernel timing ----------------------------------------------------------
 enum TimingFamily { kTimePlain = 0, kTimeBatched = 1 };
 
+bool timing_enabled();
+
 // Brackets one kernel launch with HIP events on stream `s` when timing is on.
 class TimedLaunch {
  public:
@@ -98,5 +100,6 @@ int choose_path(tq_db *db, int requested, int nq, int k);
 int search_batched(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids, int32_t *scores,
                    const tq_search_opts *opts, hipStream_t s);
 void batched_release(tq_db *db);
+int autotune(tq_db *db, int nq_max, const int *ks, int nks, hipStream_t s, int verbose);
 
 }  // namespace tqr

@@ -37,7 +37,7 @@ TQ_MAX_K = 512
 # Every function declared in include/tq.h (checked by the tests).
 EXPORTS = (
     "tq_status_str", "tq_last_error", "tq_version", "tq_code_words", "tq_encode", "tq_db_create",
-    "tq_db_export", "tq_db_info", "tq_db_destroy", "tq_search_knn", "tq_delta_dump", "tq_sync",
+    "tq_db_export", "tq_db_info", "tq_db_destroy", "tq_search_knn", "tq_autotune", "tq_delta_dump", "tq_sync",
     "tq_serve_create", "tq_serve_submit", "tq_serve_poll", "tq_serve_wait", "tq_serve_cancel",
     "tq_serve_stats", "tq_serve_destroy", "tq_timing_enable", "tq_timing_read",
 )
@@ -91,6 +91,7 @@ def lib(path: Optional[str] = None):
         "tq_db_info": ([vp, P(i64), P(i32), P(i32), P(sz)], i32),
         "tq_db_destroy": ([vp], i32),
         "tq_search_knn": ([vp, vp, i32, i32, vp, vp, P(tq_search_opts), vp], i32),
+        "tq_autotune": ([vp, i32, P(i32), i32, vp], i32),
         "tq_delta_dump": ([vp, vp, i32, vp, vp], i32),
         "tq_sync": ([vp], i32),
         "tq_serve_create": ([vp, P(tq_serve_cfg), P(vp)], i32),
@@ -257,6 +258,13 @@ def tq_search_knn(db: tq_db, qcodes: torch.Tensor, k: int, path: int = TQ_PATH_A
                                    _dev(ids, "ids", torch.int32), _dev(scores, "scores", torch.int32),
                                    ctypes.byref(o), _stream(qcodes, stream)), "tq_search_knn")
     return ids, scores
+
+
+def tq_autotune(db: tq_db, nq_max: int, ks, stream=None) -> None:
+    """Pick the fastest batched / plain shapes per batch-size bucket and k."""
+    arr = (ctypes.c_int * len(ks))(*[int(k) for k in ks])
+    with torch.cuda.device(db.device):
+        _check(lib().tq_autotune(db.handle, int(nq_max), arr, len(ks), _stream(None, stream)), "tq_autotune")
 
 
 def tq_delta_dump(db: tq_db, qcodes: torch.Tensor, stream=None) -> torch.Tensor:

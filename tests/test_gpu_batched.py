@@ -1,0 +1,146 @@
+"""Batched path (persistent query-tile kernel, hipGraph per bucket, autotuner)
+against the CPU oracle, bit-exact."""
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from tests.libtq import ensure_built
+from workloads import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stderr.flush()
+
+
+@pytest.fixture(scope="module")
+def tq():
+    return ensure_built()
+
+
+@pytest.fixture(scope="module")
+def o():
+    return oracle.default()
+
+
+def dev_codes(c):
+    return torch.from_numpy(np.ascontiguousarray(c).view(np.int32).copy()).cuda()
+
+
+@pytest.fixture(scope="module")
+def small(tq, o):
+    w = datagen.WORKLOADS["small"]
+    X = datagen.rows("small", datagen.DB, 0, w["n"]).numpy()
+    Q = datagen.rows("small", datagen.QUERIES, 0, 1500).numpy()
+    V, VQ = o.encode(X, w["x"]), o.encode(Q, w["x"])
+    db = tq.tq_db_create(dev_codes(o.pack(V)), w["d"], w["x"])
+    yield dict(V=V, VQ=VQ, CQ=o.pack(VQ), db=db)
+    db.destroy()
+
+
+def run(tq, db, CQ, k, **kw):
+    ids, sc = tq.tq_search_knn(db, dev_codes(CQ), k, **kw)
+    torch.cuda.synchronize()
+    return ids.cpu().numpy(), sc.cpu().numpy()
+
+
+@pytest.mark.parametrize("k", [1, 10, 64, 100, 128, 200, 512])
+@pytest.mark.parametrize("nq", [1, 3, 17, 100])
+def test_batched_vs_oracle(tq, o, small, k, nq):
+    say(f"batched small k={k} nq={nq}")
+    ids, sc = run(tq, small["db"], small["CQ"][:nq], k, path=tq.TQ_PATH_BATCHED)
+    ei, es = o.knn(small["VQ"][:nq], small["V"], k)
+    assert np.array_equal(sc, es) and np.array_equal(ids, ei)
+
+
+@pytest.mark.parametrize("qtile", [2, 4, 8, 16])
+@pytest.mark.parametrize("grid", [1, 5, 64, 512])
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_batched_shapes(tq, o, small, qtile, grid, use_graph):
+    k, nq = 10, 37
+    say(f"batched small qtile={qtile} grid={grid} graph={use_graph}")
+    ids, sc = run(tq, small["db"], small["CQ"][:nq], k, path=tq.TQ_PATH_BATCHED, qtile=qtile, grid=grid,
+                  use_graph=use_graph)
+    ei, es = o.knn(small["VQ"][:nq], small["V"], k)
+    assert np.array_equal(sc, es) and np.array_equal(ids, ei)
+
+
+def test_batched_graph_replays(tq, o, small):
+    """One bucket's graph replayed with different inputs and sizes, with other
+    GPU work and host synchronisation between replays; every replay checked."""
+    k = 10
+    rng = np.random.default_rng(3)
+    junk = torch.zeros(1 << 20, device="cuda")
+    for rep in range(6):
+        nq = int(rng.integers(33, 65))  # bucket 64 every time
+        q0 = int(rng.integers(0, 1400))
+        say(f"graph replay {rep} nq={nq} q0={q0}")
+        junk.add_(1.0)
+        junk.sum().item()
+        ids, sc = run(tq, small["db"], small["CQ"][q0:q0 + nq], k, path=tq.TQ_PATH_BATCHED, use_graph=1)
+        ei, es = o.knn(small["VQ"][q0:q0 + nq], small["V"], k)
+        assert np.array_equal(sc, es) and np.array_equal(ids, ei), rep
+
+
+def test_batched_many_queries(tq, o, small):
+    """More than one 1024-query chunk in one call."""
+    k = 10
+    say("batched small nq=1500")
+    ids, sc = run(tq, small["db"], small["CQ"], k, path=tq.TQ_PATH_BATCHED)
+    ei, es = o.knn(small["VQ"], small["V"], k)
+    assert np.array_equal(sc, es) and np.array_equal(ids, ei)
+
+
+@pytest.mark.parametrize("n,d,k", [(1, 16, 1), (65, 100, 65), (130, 200, 100), (1007, 384, 300),
+                                   (4160, 768, 512), (3000, 1024, 17)])
+def test_batched_ragged(tq, o, n, d, k):
+    rng = np.random.default_rng(n * 11 + d)
+    x = max(1, d // 3)
+    V = o.encode(rng.standard_normal((n, d)).astype(np.float32), x)
+    VQ = o.encode(rng.standard_normal((9, d)).astype(np.float32), x)
+    say(f"batched ragged n={n} d={d} k={k}")
+    db = tq.tq_db_create(dev_codes(o.pack(V)), d, x)
+    ids, sc = run(tq, db, o.pack(VQ), k, path=tq.TQ_PATH_BATCHED)
+    ei, es = o.knn(VQ, V, k)
+    assert np.array_equal(sc, es) and np.array_equal(ids, ei)
+    db.destroy()
+
+
+def test_batched_heavy_ties(tq, o):
+    rng = np.random.default_rng(22)
+    d, x = 256, 64
+    base = o.encode(rng.standard_normal((6, d)).astype(np.float32), x)
+    V = base[rng.integers(0, 6, size=20000)]
+    VQ = np.concatenate([base[:3], o.encode(rng.standard_normal((20, d)).astype(np.float32), x)])
+    say("batched heavy ties")
+    db = tq.tq_db_create(dev_codes(o.pack(V)), d, x)
+    for k in (1, 10, 100, 512):
+        ids, sc = run(tq, db, o.pack(VQ), k, path=tq.TQ_PATH_BATCHED)
+        ei, es = o.knn(VQ, V, k)
+        assert np.array_equal(sc, es) and np.array_equal(ids, ei), k
+    db.destroy()
+
+
+def test_batched_rejects_bad_qtile(tq, small):
+    q = dev_codes(small["CQ"][:4])
+    for qt in (3, 32):
+        with pytest.raises(tq.TQError):
+            tq.tq_search_knn(small["db"], q, 10, path=tq.TQ_PATH_BATCHED, qtile=qt)
+    with pytest.raises(tq.TQError):  # k = 300 supports query tiles up to 8
+        tq.tq_search_knn(small["db"], q, 300, path=tq.TQ_PATH_BATCHED, qtile=16)
+
+
+def test_autotune_then_auto(tq, o, small, tmp_path, monkeypatch):
+    say("autotune small then auto path")
+    tq.tq_autotune(small["db"], 64, [10, 100])
+    for nq in (1, 2, 5, 64):
+        for k in (10, 100):
+            ids, sc = run(tq, small["db"], small["CQ"][:nq], k, path=tq.TQ_PATH_AUTO)
+            ei, es = o.knn(small["VQ"][:nq], small["V"], k)
+            assert np.array_equal(sc, es) and np.array_equal(ids, ei), (nq, k)
