@@ -169,6 +169,9 @@ def main():
     avg_launch_ms = kern_ms / launches if launches else float("nan")
     achieved = db_bytes / (avg_launch_ms * 1e-3) / 1e9 if launches else float("nan")
 
+    # batched path: dominant kernel is bound by integer VALU issue, not HBM
+    valu_peak_tops = 256 * 64 * 2.4e9 / 1e12  # 32-bit lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
+    ops_per_pair = 5 * 4 * ((W + 3) // 4)  # and, xor, and + two popcount-accumulates per plane word
     traffic = None
     tf = os.path.join(ROOT, "profiles", "traffic.json")
     key = f"scan_plain/{args.workload}"
@@ -206,6 +209,15 @@ def main():
                      "traffic": traffic, "bytes_per_launch": db_bytes,
                      "avg_launch_ms": round(avg_launch_ms, 5), "launches": launches},
     }
+    if args.path == "batched":
+        ops = B * n * ops_per_pair
+        tops = ops / (avg_launch_ms * 1e-3) / 1e12
+        result["hbm_gbps"] = None
+        result["hbm_frac"] = None
+        result["roofline"] = {"kernel": "scan_batched_kernel", "bound": "alu", "achieved": round(tops, 2),
+                              "peak": round(valu_peak_tops, 2), "unit": "Tops/s", "frac": round(tops / valu_peak_tops, 4),
+                              "traffic": None, "ops_per_launch": ops, "ops_per_pair": ops_per_pair,
+                              "avg_launch_ms": round(avg_launch_ms, 5), "launches": launches}
 
     if args.copy_probe:
         a = torch.empty(1 << 28, dtype=torch.int32, device=dev)

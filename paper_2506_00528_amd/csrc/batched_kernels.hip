@@ -23,8 +23,24 @@ constexpr int kBatchWaves = 4;
 constexpr int kBatchBlock = 64 * kBatchWaves;
 
 // Canonical query codes -> nz/ng words padded to 4*nc per plane (the layout
-// the scan reads); writes the call's parameters.  Threads past the real
-// queries write zeros for the bucket's padding rows.
+// the scan reads); rows in [nq, rows) are written as zeros.
+__global__ __launch_bounds__(256) void prep_rows_kernel(const uint32_t *__restrict__ qcodes, int nq, int rows, int W,
+                                                        int nc, uint32_t *__restrict__ qprep) {
+  const int W4 = 4 * nc;
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= static_cast<int64_t>(rows) * W4) return;
+  const int q = static_cast<int>(g / W4);
+  const int w = static_cast<int>(g - static_cast<int64_t>(q) * W4);
+  uint32_t p = 0, m = 0;
+  if (q < nq && w < W) {
+    p = qcodes[static_cast<int64_t>(q) * 2 * W + w];
+    m = qcodes[static_cast<int64_t>(q) * 2 * W + W + w];
+  }
+  qprep[static_cast<int64_t>(q) * 2 * W4 + w] = p | m;
+  qprep[static_cast<int64_t>(q) * 2 * W4 + W4 + w] = m;
+}
+
+// Query rows for one search call plus the call's parameters.
 __global__ __launch_bounds__(256) void batch_prep_kernel(const uint32_t *__restrict__ qcodes, int nq, int bucket,
                                                          int W, int nc, int qtile, int grid, int64_t ntiles,
                                                          int32_t *ids, int32_t *scores, uint32_t *__restrict__ qprep,
@@ -44,17 +60,32 @@ __global__ __launch_bounds__(256) void batch_prep_kernel(const uint32_t *__restr
   }
   if (g == 0) {
     BatchParams b;
-    b.nq = nq;
-    b.nqt = (nq + qtile - 1) / qtile;
-    int64_t parts = (grid + b.nqt - 1) / b.nqt;
-    if (parts > ntiles) parts = ntiles;
-    if (parts < 1) parts = 1;
-    b.parts = static_cast<int>(parts);
-    b.tiles_per_part = (ntiles + parts - 1) / parts;
+    batch_split(b, nq, qtile, grid, 0, ntiles);
+    b.slots = nullptr;
+    b.running = nullptr;
     b.ids = ids;
     b.scores = scores;
     *prm = b;
   }
+}
+
+__global__ __launch_bounds__(256) void fill_zero_kernel(uint64_t *__restrict__ p, int64_t count) {
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g < count) p[g] = 0;
+}
+
+__global__ __launch_bounds__(256) void running_results_kernel(const uint64_t *__restrict__ running,
+                                                              const int *__restrict__ slots, int count, int k,
+                                                              int32_t *__restrict__ ids,
+                                                              int32_t *__restrict__ scores) {
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= static_cast<int64_t>(count) * k) return;
+  const int i = static_cast<int>(g / k);
+  const int j = static_cast<int>(g - static_cast<int64_t>(i) * k);
+  const int64_t at = static_cast<int64_t>(slots[i]) * k + j;
+  const uint64_t key = running[at];
+  ids[at] = key ? key_id(key) : -1;
+  scores[at] = key ? key_score(key) : 0;
 }
 
 template <int NC, int R, int QT>
@@ -68,6 +99,8 @@ __global__ __launch_bounds__(kBatchBlock) void scan_batched_kernel(const uint4 *
   const int wave = threadIdx.x >> 6;
   const int nq = prm->nq, nqt = prm->nqt, parts = prm->parts;
   const int64_t tpp = prm->tiles_per_part;
+  const int64_t tile_lo = prm->tile_lo, tile_hi = prm->tile_hi;
+  const int *__restrict__ slots = prm->slots;
   const int items = nqt * parts;
   const int km1 = k - 1;
 
@@ -76,8 +109,8 @@ __global__ __launch_bounds__(kBatchBlock) void scan_batched_kernel(const uint4 *
     const int part = item / nqt;
     const int q0 = qt * QT;
     const int nact = min(QT, nq - q0);
-    const int64_t t0 = static_cast<int64_t>(part) * tpp;
-    const int64_t t1 = min(ntiles, t0 + tpp);
+    const int64_t t0 = tile_lo + static_cast<int64_t>(part) * tpp;
+    const int64_t t1 = min(tile_hi, t0 + tpp);
 
     WaveList<R> list[QT];
     uint64_t thr[QT];
@@ -100,7 +133,8 @@ __global__ __launch_bounds__(kBatchBlock) void scan_batched_kernel(const uint4 *
 #pragma unroll
       for (int qi = 0; qi < QT; ++qi) {
         if (qi < nact) {
-          const uint32_t *qw = qprep + static_cast<int64_t>(q0 + qi) * (8 * NC);
+          const int row = slots ? slots[q0 + qi] : q0 + qi;
+          const uint32_t *qw = qprep + static_cast<int64_t>(row) * (8 * NC);
           DeltaAcc a;
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
@@ -180,6 +214,29 @@ hipError_t batch_prep_launch(const uint32_t *qcodes, int nq, int bucket, const D
   const unsigned blocks = static_cast<unsigned>((threads + 255) / 256);
   hipLaunchKernelGGL(batch_prep_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, qcodes, nq, bucket, db.W,
                      db.nc, qtile, grid, db.ntiles, ids, scores, qprep, prm);
+  return hipGetLastError();
+}
+
+hipError_t prep_rows_launch(const uint32_t *qcodes, int nq, const DbDev &db, uint32_t *rows, hipStream_t s) {
+  const int64_t threads = static_cast<int64_t>(nq) * 4 * db.nc;
+  if (threads == 0) return hipSuccess;
+  hipLaunchKernelGGL(prep_rows_kernel, dim3(static_cast<unsigned>((threads + 255) / 256)), dim3(256), 0, s, qcodes,
+                     nq, nq, db.W, db.nc, rows);
+  return hipGetLastError();
+}
+
+hipError_t fill_zero_launch(uint64_t *p, int64_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(static_cast<unsigned>((count + 255) / 256)), dim3(256), 0, s, p, count);
+  return hipGetLastError();
+}
+
+hipError_t running_results_launch(const uint64_t *running, const int *slots, int count, int k, int32_t *ids,
+                                  int32_t *scores, hipStream_t s) {
+  const int64_t threads = static_cast<int64_t>(count) * k;
+  if (threads == 0) return hipSuccess;
+  hipLaunchKernelGGL(running_results_kernel, dim3(static_cast<unsigned>((threads + 255) / 256)), dim3(256), 0, s,
+                     running, slots, count, k, ids, scores);
   return hipGetLastError();
 }
 

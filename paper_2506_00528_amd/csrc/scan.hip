@@ -71,16 +71,18 @@ __global__ __launch_bounds__(kMergeBlock) void merge_lists_kernel(const uint64_t
                                                                   const BatchParams *__restrict__ prm) {
   __shared__ uint64_t buf[2][kMergeLdsKeys];
   const int q = blockIdx.x;
+  uint64_t *running = nullptr;
   if (prm) {
     if (q >= prm->nq) return;
     nlists = prm->parts;
     ids = prm->ids;
     scores = prm->scores;
+    if (prm->running) running = prm->running + static_cast<int64_t>(prm->slots ? prm->slots[q] : q) * k;
   }
   const uint64_t *lists = partial + static_cast<int64_t>(q) * nlists * k;
   uint64_t *a = buf[0];
   uint64_t *b = buf[1];
-  for (int i = threadIdx.x; i < k; i += kMergeBlock) a[i] = 0;
+  for (int i = threadIdx.x; i < k; i += kMergeBlock) a[i] = running ? running[i] : 0ull;
   for (int l0 = 0; l0 < nlists; l0 += chunk - 1) {
     const int take = min(chunk - 1, nlists - l0);
     for (int i = threadIdx.x; i < (chunk - 1) * k; i += kMergeBlock) {
@@ -95,8 +97,12 @@ __global__ __launch_bounds__(kMergeBlock) void merge_lists_kernel(const uint64_t
   }
   for (int i = threadIdx.x; i < k; i += kMergeBlock) {
     const uint64_t key = a[i];
-    ids[static_cast<int64_t>(q) * k + i] = key ? key_id(key) : -1;
-    scores[static_cast<int64_t>(q) * k + i] = key ? key_score(key) : 0;
+    if (running) {
+      running[i] = key;
+    } else {
+      ids[static_cast<int64_t>(q) * k + i] = key ? key_id(key) : -1;
+      scores[static_cast<int64_t>(q) * k + i] = key ? key_score(key) : 0;
+    }
   }
 }
 

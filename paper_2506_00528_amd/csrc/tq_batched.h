@@ -15,9 +15,30 @@ struct BatchParams {
   int parts;               // database parts: the grid gets nqt * parts work items
   int pad;
   int64_t tiles_per_part;  // 64-vector tiles per part
-  int32_t *ids;            // caller's outputs, nq x k
+  int64_t tile_lo;         // database tiles scanned: [tile_lo, tile_hi)
+  int64_t tile_hi;
+  const int *slots;        // optional: query i lives in row slots[i] of the query
+                           // and running buffers (else row i)
+  uint64_t *running;       // optional: per-row running top-k (k keys) merged with
+                           // this pass and written back instead of ids / scores
+  int32_t *ids;            // caller's outputs, nq x k (when running is null)
   int32_t *scores;
 };
+
+// Host-side fill of the derived split of a batch over tiles [lo, hi).
+__host__ __device__ inline void batch_split(BatchParams &b, int nq, int qtile, int grid, int64_t lo, int64_t hi) {
+  b.nq = nq;
+  b.nqt = (nq + qtile - 1) / qtile;
+  const int64_t ntiles = hi - lo;
+  int64_t parts = b.nqt > 0 ? (grid + b.nqt - 1) / b.nqt : 1;
+  if (parts > ntiles) parts = ntiles;
+  if (parts < 1) parts = 1;
+  b.parts = static_cast<int>(parts);
+  b.pad = 0;
+  b.tiles_per_part = (ntiles + parts - 1) / parts;
+  b.tile_lo = lo;
+  b.tile_hi = hi;
+}
 
 // Largest query tile the batched scan supports for this k.
 int batched_max_qtile(int k);
@@ -27,8 +48,19 @@ hipError_t batch_prep_launch(const uint32_t *qcodes, int nq, int bucket, const D
 hipError_t scan_batched_launch(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile,
                                int grid, uint64_t *partial, hipStream_t s);
 // Per-query merge of the (query, part) lists; the query count, part count and
-// output pointers come from `prm`; `bucket` workgroups are launched.
+// output pointers come from `prm`; `bucket` workgroups are launched.  With
+// prm->running set, each query's running list joins the merge and receives
+// the result.
 hipError_t merge_batched_launch(const uint64_t *partial, const BatchParams *prm, int bucket, int k,
                                 hipStream_t s);
+
+// Canonical query codes -> nz/ng rows (the layout the batched scan reads).
+hipError_t prep_rows_launch(const uint32_t *qcodes, int nq, const DbDev &db, uint32_t *rows, hipStream_t s);
+// Zero `count` 64-bit words (a fill kernel, safe inside captured graphs).
+hipError_t fill_zero_launch(uint64_t *p, int64_t count, hipStream_t s);
+// ids / scores from the running lists of rows slots[0..count): row slots[i]
+// of `ids` / `scores` (k per row) receives that row's result.
+hipError_t running_results_launch(const uint64_t *running, const int *slots, int count, int k, int32_t *ids,
+                                  int32_t *scores, hipStream_t s);
 
 }  // namespace tqi

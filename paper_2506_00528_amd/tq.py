@@ -284,3 +284,77 @@ def tq_timing_read(which: int = 0, reset: bool = False) -> Tuple[float, int]:
     ms, n = ctypes.c_double(), ctypes.c_int64()
     _check(lib().tq_timing_read(int(which), ctypes.byref(ms), ctypes.byref(n), int(bool(reset))), "tq_timing_read")
     return ms.value, n.value
+
+
+class tq_server:
+    """Continuous-batching server over a database (tq_serve_create / destroy).
+
+    submit() takes host query codes (numpy uint32 / int32, nq x 2W) and returns
+    a ticket; poll() / wait() return (ids, scores, stats) as numpy arrays once
+    the request has finished, or None while it is pending."""
+
+    def __init__(self, db: tq_db, budget_bytes: int = 0, max_slots: int = 0, max_k: int = 0, n_segments: int = 0,
+                 max_request_nq: int = 0):
+        import numpy as np  # noqa: F401
+        self.db = db
+        cfg = tq_serve_cfg()
+        cfg.budget_bytes, cfg.max_slots, cfg.max_k = int(budget_bytes), int(max_slots), int(max_k)
+        cfg.n_segments, cfg.max_request_nq = int(n_segments), int(max_request_nq)
+        self._h = ctypes.c_void_p()
+        self._k = {}
+        with torch.cuda.device(db.device):
+            _check(lib().tq_serve_create(db.handle, ctypes.byref(cfg), ctypes.byref(self._h)), "tq_serve_create")
+
+    def submit(self, qcodes, k: int) -> int:
+        import numpy as np
+        q = np.ascontiguousarray(qcodes).view(np.uint32)
+        if q.ndim != 2 or q.shape[1] != 2 * self.db.W:
+            raise ValueError("qcodes must be nq x 2W")
+        t = ctypes.c_uint64()
+        _check(lib().tq_serve_submit(self._h, q.ctypes.data, q.shape[0], int(k), ctypes.byref(t)), "tq_serve_submit")
+        self._k[t.value] = (q.shape[0], int(k))
+        return t.value
+
+    def _collect(self, fn, ticket, *extra):
+        import numpy as np
+        nq, k = self._k.get(ticket, (1, 1))
+        ids = np.empty((nq, k), np.int32)
+        sc = np.empty((nq, k), np.int32)
+        st = tq_req_stats()
+        rc = fn(self._h, ctypes.c_uint64(ticket), *extra, ids.ctypes.data, sc.ctypes.data, ctypes.byref(st))
+        if rc == TQ_ERR_AGAIN:
+            return None
+        _check(rc, fn.__name__)
+        self._k.pop(ticket, None)
+        return ids, sc, st
+
+    def poll(self, ticket: int):
+        return self._collect(lib().tq_serve_poll, ticket)
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        return self._collect(lib().tq_serve_wait, ticket, ctypes.c_int(int(timeout_ms)))
+
+    def cancel(self, ticket: int) -> None:
+        _check(lib().tq_serve_cancel(self._h, ctypes.c_uint64(ticket)), "tq_serve_cancel")
+        self._k.pop(ticket, None)
+
+    def stats(self):
+        a, b, c, d = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().tq_serve_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)),
+               "tq_serve_stats")
+        return dict(submitted=a.value, completed=b.value, ticks=c.value, bytes_in_use=d.value)
+
+    def destroy(self) -> None:
+        if self._h:
+            _check(lib().tq_serve_destroy(self._h), "tq_serve_destroy")
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def tq_serve_create(db: tq_db, **cfg) -> tq_server:
+    return tq_server(db, **cfg)
