@@ -293,7 +293,7 @@ static int time_config(tq_db *db, const uint32_t *q, int nq, int k, int32_t *ids
     return fail(TQ_ERR_DEVICE, "hipEventCreate");
   int rc = TQ_OK;
   float best = 1e30f;
-  for (int rep = 0; rep < 3 && rc == TQ_OK; ++rep) {
+  for (int rep = 0; rep < 2 && rc == TQ_OK; ++rep) {
     (void)hipEventRecord(a, s);
     if (sh.plain)
       rc = search_plain(db, q, nq, k, ids, scores, 0, s);
@@ -311,28 +311,7 @@ static int time_config(tq_db *db, const uint32_t *q, int nq, int k, int32_t *ids
   return rc;
 }
 
-int autotune_view(tq_db *db, int nq_max, const int *ks, int nks, hipStream_t s, int verbose);
-
-// Shapes are timed on the first kTunePrefix vectors of the database (a full
-// pass of a large database per candidate would make tuning slow); graphs and
-// buffers built on that prefix view are dropped afterwards.
-constexpr int64_t kTunePrefix = int64_t(1) << 21;
-
 int autotune(tq_db *db, int nq_max, const int *ks, int nks, hipStream_t s, int verbose) {
-  const tqi::DbDev full = db->dev;
-  batched_release(db);
-  if (db->dev.n > kTunePrefix) {
-    db->dev.n = kTunePrefix;
-    db->dev.ntiles = kTunePrefix / tqi::kTileVecs;
-  }
-  int rc = autotune_view(db, nq_max, ks, nks, s, verbose);
-  (void)hipStreamSynchronize(s);
-  batched_release(db);
-  db->dev = full;
-  return rc;
-}
-
-int autotune_view(tq_db *db, int nq_max, const int *ks, int nks, hipStream_t s, int verbose) {
   const int maxb = bucket_of(std::min(std::max(nq_max, 1), kMaxBucket));
   // queries: copies of the first database rows (valid codes of the right (d, x))
   const int nqq = std::min<int64_t>(maxb, db->dev.n);
@@ -366,11 +345,12 @@ int autotune_view(tq_db *db, int nq_max, const int *ks, int nks, hipStream_t s, 
       std::vector<Shape> cands;
       Shape p;
       p.plain = true;
-      if (b <= 16) cands.push_back(p);
-      for (int qt : {2, 4, 8, 16}) {
-        if (qt > tqi::batched_max_qtile(k) || qt > 2 * b) continue;
-        if (qt < 4 && b > 8) continue;
-        for (int gm : {1, 2, 4}) {
+      if (b <= 8) cands.push_back(p);
+      // the two largest query tiles that the bucket can fill, on 2x / 4x CU workgroups
+      const int qmax = std::min(tqi::batched_max_qtile(k), std::max(2, b));
+      for (int qt : {qmax / 2, qmax}) {
+        if (qt < 2) continue;
+        for (int gm : {2, 4}) {
           Shape c;
           c.qtile = qt;
           c.grid = cu * gm;

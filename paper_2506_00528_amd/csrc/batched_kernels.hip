@@ -69,6 +69,17 @@ __global__ __launch_bounds__(256) void batch_prep_kernel(const uint32_t *__restr
   }
 }
 
+// rows[i] = src[slots[i]] for rows of `words` 32-bit words.
+__global__ __launch_bounds__(256) void gather_rows_kernel(const uint32_t *__restrict__ src,
+                                                          const int *__restrict__ slots, int count, int words,
+                                                          uint32_t *__restrict__ rows) {
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= static_cast<int64_t>(count) * words) return;
+  const int i = static_cast<int>(g / words);
+  const int w = static_cast<int>(g - static_cast<int64_t>(i) * words);
+  rows[g] = src[static_cast<int64_t>(slots[i]) * words + w];
+}
+
 __global__ __launch_bounds__(256) void fill_zero_kernel(uint64_t *__restrict__ p, int64_t count) {
   const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (g < count) p[g] = 0;
@@ -100,7 +111,6 @@ __global__ __launch_bounds__(kBatchBlock) void scan_batched_kernel(const uint4 *
   const int nq = prm->nq, nqt = prm->nqt, parts = prm->parts;
   const int64_t tpp = prm->tiles_per_part;
   const int64_t tile_lo = prm->tile_lo, tile_hi = prm->tile_hi;
-  const int *__restrict__ slots = prm->slots;
   const int items = nqt * parts;
   const int km1 = k - 1;
 
@@ -133,8 +143,7 @@ __global__ __launch_bounds__(kBatchBlock) void scan_batched_kernel(const uint4 *
 #pragma unroll
       for (int qi = 0; qi < QT; ++qi) {
         if (qi < nact) {
-          const int row = slots ? slots[q0 + qi] : q0 + qi;
-          const uint32_t *qw = qprep + static_cast<int64_t>(row) * (8 * NC);
+          const uint32_t *qw = qprep + static_cast<int64_t>(q0 + qi) * (8 * NC);
           DeltaAcc a;
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
@@ -222,6 +231,15 @@ hipError_t prep_rows_launch(const uint32_t *qcodes, int nq, const DbDev &db, uin
   if (threads == 0) return hipSuccess;
   hipLaunchKernelGGL(prep_rows_kernel, dim3(static_cast<unsigned>((threads + 255) / 256)), dim3(256), 0, s, qcodes,
                      nq, nq, db.W, db.nc, rows);
+  return hipGetLastError();
+}
+
+hipError_t gather_rows_launch(const uint32_t *src, const int *slots, int count, int words, uint32_t *rows,
+                              hipStream_t s) {
+  const int64_t threads = static_cast<int64_t>(count) * words;
+  if (threads == 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_rows_kernel, dim3(static_cast<unsigned>((threads + 255) / 256)), dim3(256), 0, s, src,
+                     slots, count, words, rows);
   return hipGetLastError();
 }
 

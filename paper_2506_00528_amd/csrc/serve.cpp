@@ -89,7 +89,8 @@ struct tq_server {
 
   // device
   uint32_t *d_qcanon = nullptr;  // max_slots x 2W
-  uint32_t *d_qrows = nullptr;   // max_slots x 8 nc
+  uint32_t *d_qrows = nullptr;   // max_slots x 8 nc, by slot
+  uint32_t *d_qtick = nullptr;   // max_slots x 8 nc, the active rows of a tick, compact
   uint64_t *d_running = nullptr; // max_slots x k_run
   uint64_t *d_partial = nullptr; // (qtile * grid + max_slots) x k_run
   tqi::BatchParams *d_prm = nullptr;
@@ -214,9 +215,11 @@ hipError_t enqueue_tick(tq_server *s, TickPlan &p, TickStage &st) {
   if (e != hipSuccess) return e;
   st.used = true;
   // scan the segment for every active query and fold it into the running lists
+  e = tqi::gather_rows_launch(s->d_qrows, s->d_slots, nq, 8 * db.nc, s->d_qtick, s->stream);
+  if (e != hipSuccess) return e;
   {
     TimedLaunch t(kTimeBatched, s->stream);
-    e = tqi::scan_batched_launch(db, s->d_qrows, s->d_prm, s->k_run, s->qtile, s->grid, s->d_partial, s->stream);
+    e = tqi::scan_batched_launch(db, s->d_qtick, s->d_prm, s->k_run, s->qtile, s->grid, s->d_partial, s->stream);
   }
   if (e != hipSuccess) return e;
   e = tqi::merge_batched_launch(s->d_partial, s->d_prm, nq, s->k_run, s->stream);
@@ -365,7 +368,7 @@ void serve_loop(tq_server *s) {
 
 void free_server(tq_server *s) {
   if (s->stream) (void)hipStreamSynchronize(s->stream);
-  for (void *p : {(void *)s->d_qcanon, (void *)s->d_qrows, (void *)s->d_running, (void *)s->d_partial,
+  for (void *p : {(void *)s->d_qcanon, (void *)s->d_qrows, (void *)s->d_qtick, (void *)s->d_running, (void *)s->d_partial,
                   (void *)s->d_prm, (void *)s->d_slots, (void *)s->d_retire, (void *)s->d_ids, (void *)s->d_scores})
     if (p) (void)hipFree(p);
   for (void *p : {(void *)s->h_qcanon, (void *)s->h_ids, (void *)s->h_scores})
@@ -420,7 +423,7 @@ int tq_serve_create(const tq_db *db, const tq_serve_cfg *cfg, tq_server **out) {
   s->S = static_cast<int>((ntiles + s->seg_tiles - 1) / s->seg_tiles);
   s->cfg.n_segments = s->S;
   const int W = db->dev.W, nc = db->dev.nc;
-  s->per_query_bytes = static_cast<size_t>(2 * W + 8 * nc) * sizeof(uint32_t) +
+  s->per_query_bytes = static_cast<size_t>(2 * W + 16 * nc) * sizeof(uint32_t) +
                        static_cast<size_t>(s->k_run) * (sizeof(uint64_t) + 2 * sizeof(int32_t));
   s->slot_used.assign(c.max_slots, 0);
 
@@ -435,6 +438,7 @@ int tq_serve_create(const tq_db *db, const tq_serve_cfg *cfg, tq_server **out) {
   };
   dm((void **)&s->d_qcanon, M * 2 * W * sizeof(uint32_t));
   dm((void **)&s->d_qrows, M * 8 * nc * sizeof(uint32_t));
+  dm((void **)&s->d_qtick, M * 8 * nc * sizeof(uint32_t));
   dm((void **)&s->d_running, M * s->k_run * sizeof(uint64_t));
   dm((void **)&s->d_partial, (static_cast<size_t>(s->qtile) * s->grid + M) * s->k_run * sizeof(uint64_t));
   dm((void **)&s->d_prm, sizeof(tqi::BatchParams));

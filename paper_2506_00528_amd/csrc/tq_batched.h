@@ -17,8 +17,9 @@ struct BatchParams {
   int64_t tiles_per_part;  // 64-vector tiles per part
   int64_t tile_lo;         // database tiles scanned: [tile_lo, tile_hi)
   int64_t tile_hi;
-  const int *slots;        // optional: query i lives in row slots[i] of the query
-                           // and running buffers (else row i)
+  const int *slots;        // optional: query i's running list is row slots[i] of
+                           // `running` (else row i); the scan always reads query
+                           // rows compactly (row i for query i)
   uint64_t *running;       // optional: per-row running top-k (k keys) merged with
                            // this pass and written back instead of ids / scores
   int32_t *ids;            // caller's outputs, nq x k (when running is null)
@@ -56,6 +57,9 @@ hipError_t merge_batched_launch(const uint64_t *partial, const BatchParams *prm,
 
 // Canonical query codes -> nz/ng rows (the layout the batched scan reads).
 hipError_t prep_rows_launch(const uint32_t *qcodes, int nq, const DbDev &db, uint32_t *rows, hipStream_t s);
+// rows[i] = src[slots[i]] for `count` rows of `words` 32-bit words.
+hipError_t gather_rows_launch(const uint32_t *src, const int *slots, int count, int words, uint32_t *rows,
+                              hipStream_t s);
 // Zero `count` 64-bit words (a fill kernel, safe inside captured graphs).
 hipError_t fill_zero_launch(uint64_t *p, int64_t count, hipStream_t s);
 // ids / scores from the running lists of rows slots[0..count): row slots[i]

@@ -95,7 +95,7 @@ def test_alone_and_in_the_mix(tq, env, segments):
 
 def test_budget_admission(tq, env):
     W, nc = env["W"], (env["W"] + 3) // 4
-    per_query = (2 * W + 8 * nc) * 4 + 100 * 16
+    per_query = (2 * W + 16 * nc) * 4 + 100 * 16
     srv = tq.tq_server(env["db"], max_k=100, n_segments=2, budget_bytes=per_query * 5)
     say("serve budget: oversize request rejected")
     with pytest.raises(tq.TQError) as e:
