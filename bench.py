@@ -55,6 +55,7 @@ def parse():
     p.add_argument("--batches", type=int, default=500)
     p.add_argument("--no-serving", action="store_true", help="skip the serving workload")
     p.add_argument("--serve-requests", type=int, default=2000, help="requests per arrival rate")
+    p.add_argument("--serve-segments", type=int, default=0, help="database segments per pass (0: library default)")
     return p.parse_args()
 
 
@@ -166,7 +167,8 @@ def run_serving(tq, torch, args, log):
                        f"k in {{10,100}}, {args.serve_requests} requests per rate",
            "plain_qps": round(plain_qps, 1), "plain_capacity_req_s": round(cap_req, 1),
            "recall_at_10": round(recall, 4), "rates": []}
-    srv = tq.tq_server(db, max_k=100, max_slots=8192, max_request_nq=256, budget_bytes=1 << 30)
+    srv = tq.tq_server(db, max_k=100, max_slots=8192, max_request_nq=256, budget_bytes=1 << 30,
+                       n_segments=args.serve_segments)
     for frac in wl["rates"]:
         rate = frac * cap_req
         reqs = datagen.request_stream(args.serve_requests, rate, wl["mean_size"], wl["max_size"], wl["ks"])
@@ -217,6 +219,7 @@ def run_serving(tq, torch, args, log):
     st = srv.stats()
     srv.destroy()
     out["ticks"] = st["ticks"]
+    out["segments"] = args.serve_segments or "default"
     db.destroy()
     return out
 

@@ -208,7 +208,8 @@ typedef struct tq_serve_cfg {
                             0 = 256 MiB */
   int max_slots;         /* most queries in flight at once; 0 = 4096 */
   int max_k;             /* largest k a request may ask for; 0 = 128 */
-  int n_segments;        /* database segments per pass; 0 = automatic */
+  int n_segments;        /* database segments per pass (a request needs one
+                            tick per segment); 0 = one per 16M vectors */
   int max_request_nq;    /* largest nq of one request; 0 = 1024 */
   int reserved[4];
 } tq_serve_cfg;

@@ -125,6 +125,7 @@ struct BatchEntry {
   uint32_t *qprep = nullptr;
   tqi::BatchParams *prm = nullptr;
   uint64_t *partial = nullptr;
+  uint64_t *mid = nullptr;  // first-stage merge results
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -142,6 +143,7 @@ void free_entry(BatchEntry &e) {
   if (e.qprep) (void)hipFree(e.qprep);
   if (e.prm) (void)hipFree(e.prm);
   if (e.partial) (void)hipFree(e.partial);
+  if (e.mid) (void)hipFree(e.mid);
   e = BatchEntry{};
 }
 
@@ -160,6 +162,8 @@ int get_entry(tq_db *db, hipStream_t s, int bucket, int k, const Shape &sh, Batc
   hipError_t err = hipMalloc(&e.qprep, qbytes);
   if (err == hipSuccess) err = hipMalloc(&e.prm, sizeof(tqi::BatchParams));
   if (err == hipSuccess) err = hipMalloc(&e.partial, lists * k * sizeof(uint64_t));
+  if (err == hipSuccess)
+    err = hipMalloc(&e.mid, static_cast<size_t>(tqi::merge_batched_mid_keys(bucket, sh.grid, k)) * sizeof(uint64_t));
   if (err != hipSuccess) {
     free_entry(e);
     return hip_fail(err, "hipMalloc(batched buffers)");
@@ -171,7 +175,7 @@ int get_entry(tq_db *db, hipStream_t s, int bucket, int k, const Shape &sh, Batc
 int enqueue_scan_merge(tq_db *db, BatchEntry &e, int bucket, int k, const Shape &sh, hipStream_t s) {
   hipError_t err = tqi::scan_batched_launch(db->dev, e.qprep, e.prm, k, sh.qtile, sh.grid, e.partial, s);
   if (err != hipSuccess) return hip_fail(err, "batched scan launch");
-  err = tqi::merge_batched_launch(e.partial, e.prm, bucket, k, s);
+  err = tqi::merge_batched_launch(e.partial, e.prm, bucket, k, sh.grid, e.mid, s);
   if (err != hipSuccess) return hip_fail(err, "batched merge launch");
   return TQ_OK;
 }
@@ -222,7 +226,7 @@ int run_chunk(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids, in
       err = tqi::scan_batched_launch(db->dev, e->qprep, e->prm, k, sh.qtile, sh.grid, e->partial, s);
     }
     if (err != hipSuccess) return hip_fail(err, "batched scan launch");
-    err = tqi::merge_batched_launch(e->partial, e->prm, bucket, k, s);
+    err = tqi::merge_batched_launch(e->partial, e->prm, bucket, k, sh.grid, e->mid, s);
     if (err != hipSuccess) return hip_fail(err, "batched merge launch");
     return TQ_OK;
   }

@@ -56,30 +56,59 @@ __global__ __launch_bounds__(kScanBlock) void scan_plain_kernel(const uint4 *__r
   for (int p = threadIdx.x; p < k; p += kScanBlock) partial[static_cast<int64_t>(blockIdx.x) * k + p] = res[p];
 }
 
-// Final merge: one workgroup per query.  The running result occupies list
-// slot 0 of the LDS buffer; each round loads up to chunk-1 more lists into
-// the other slots and tree-merges all of them back into slot 0.
+// Per-query merge of many sorted lists of k keys.  A workgroup tree-merges
+// the lists in LDS in rounds of `chunk` lists (slot 0 carries the running
+// result).  Many lists are merged in two stages: merge_groups_kernel gives
+// every group of gl lists its own workgroup, then merge_lists_kernel merges
+// the group results, so a query's merge is spread over several CUs.
 constexpr int kMergeBlock = 1024;
 constexpr int kMergeLdsKeys = 4096;  // per buffer (two buffers: 64 KiB)
 
-// With `prm` set (batched path) the query count, list count and outputs come
-// from the device parameter block and workgroups past the real queries exit.
-__global__ __launch_bounds__(kMergeBlock) void merge_lists_kernel(const uint64_t *__restrict__ partial,
-                                                                  int nlists, int k, int chunk,
+// Stage 1: workgroup (q, g) merges lists [g*gl, (g+1)*gl) of query q (layout
+// src[(q * nlists + l) * k]) into mid[(q * gmax + g) * k].  With `prm` the
+// query and list counts come from the device parameter block.
+__global__ __launch_bounds__(kMergeBlock) void merge_groups_kernel(const uint64_t *__restrict__ src, int nlists,
+                                                                   int k, int gl, int gmax,
+                                                                   const BatchParams *__restrict__ prm,
+                                                                   uint64_t *__restrict__ mid) {
+  __shared__ uint64_t buf[2][kMergeLdsKeys];
+  const int q = blockIdx.x, g = blockIdx.y;
+  if (prm) {
+    if (q >= prm->nq) return;
+    nlists = prm->parts;
+  }
+  const int first = g * gl;
+  if (first >= nlists) return;
+  const int take = min(gl, nlists - first);
+  const uint64_t *lists = src + (static_cast<int64_t>(q) * nlists + first) * k;
+  for (int i = threadIdx.x; i < gl * k; i += kMergeBlock) buf[0][i] = (i / k < take) ? lists[i] : 0ull;
+  const uint64_t *res = tree_merge(buf[0], buf[1], gl, k);
+  for (int i = threadIdx.x; i < k; i += kMergeBlock) mid[(static_cast<int64_t>(q) * gmax + g) * k + i] = res[i];
+}
+
+// Final stage: one workgroup per query merges its `nlists` lists (qstride
+// lists per query in `src`).  With `prm`: the query count and outputs come
+// from the parameter block; nlists = prm->parts, or ceil(prm->parts / gl_div)
+// group results when the first stage ran; with prm->running set, the query's
+// running list joins the merge and receives the result.
+__global__ __launch_bounds__(kMergeBlock) void merge_lists_kernel(const uint64_t *__restrict__ src, int nlists,
+                                                                  int qstride, int k, int chunk,
                                                                   int32_t *__restrict__ ids,
                                                                   int32_t *__restrict__ scores,
-                                                                  const BatchParams *__restrict__ prm) {
+                                                                  const BatchParams *__restrict__ prm, int gl_div) {
   __shared__ uint64_t buf[2][kMergeLdsKeys];
   const int q = blockIdx.x;
   uint64_t *running = nullptr;
   if (prm) {
     if (q >= prm->nq) return;
-    nlists = prm->parts;
+    nlists = gl_div ? (prm->parts + gl_div - 1) / gl_div : prm->parts;
+    if (!gl_div) qstride = nlists;
     ids = prm->ids;
     scores = prm->scores;
-    if (prm->running) running = prm->running + static_cast<int64_t>(prm->slots ? prm->slots[q] : q) * k;
+    if (prm->running)
+      running = prm->running + static_cast<int64_t>(prm->slots ? prm->slots[q] : q) * prm->running_stride;
   }
-  const uint64_t *lists = partial + static_cast<int64_t>(q) * nlists * k;
+  const uint64_t *lists = src + static_cast<int64_t>(q) * qstride * k;
   uint64_t *a = buf[0];
   uint64_t *b = buf[1];
   for (int i = threadIdx.x; i < k; i += kMergeBlock) a[i] = running ? running[i] : 0ull;
@@ -167,28 +196,51 @@ hipError_t scan_plain_launch(const DbDev &db, const uint32_t *qcode, int k, int 
   }
 }
 
-// Lists per merge round: a power of two with chunk * k keys in one LDS buffer.
-static int merge_chunk(int k, int nlists) {
+// Lists per merge round: the largest power of two with chunk * k keys in one
+// LDS buffer (at most 512).
+static int merge_chunk(int k) {
   int chunk = 2;
-  while (chunk * 2 * k <= kMergeLdsKeys && chunk < 2 * nlists && chunk < 512) chunk *= 2;
+  while (chunk * 2 * k <= kMergeLdsKeys && chunk < 512) chunk *= 2;
   return chunk;
 }
 
+int64_t merge_mid_keys(int nq, int nlists, int k) {
+  const int chunk = merge_chunk(k);
+  if (nlists <= chunk - 1) return 0;
+  return static_cast<int64_t>(nq) * ((nlists + chunk - 1) / chunk) * k;
+}
+
 hipError_t merge_launch(const uint64_t *partial, int nq, int nlists, int k, int32_t *ids, int32_t *scores,
-                        hipStream_t s) {
-  const int chunk = merge_chunk(k, nlists);
+                        uint64_t *mid, hipStream_t s) {
+  const int chunk = merge_chunk(k);
   if (chunk * k > kMergeLdsKeys) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(merge_lists_kernel, dim3(nq), dim3(kMergeBlock), 0, s, partial, nlists, k, chunk, ids,
-                     scores, static_cast<const BatchParams *>(nullptr));
+  if (nlists <= chunk - 1) {
+    hipLaunchKernelGGL(merge_lists_kernel, dim3(nq), dim3(kMergeBlock), 0, s, partial, nlists, nlists, k, chunk, ids,
+                       scores, static_cast<const BatchParams *>(nullptr), 0);
+    return hipGetLastError();
+  }
+  const int gmax = (nlists + chunk - 1) / chunk;
+  hipLaunchKernelGGL(merge_groups_kernel, dim3(nq, gmax), dim3(kMergeBlock), 0, s, partial, nlists, k, chunk, gmax,
+                     static_cast<const BatchParams *>(nullptr), mid);
+  hipLaunchKernelGGL(merge_lists_kernel, dim3(nq), dim3(kMergeBlock), 0, s, static_cast<const uint64_t *>(mid), gmax,
+                     gmax, k, chunk, ids, scores, static_cast<const BatchParams *>(nullptr), 0);
   return hipGetLastError();
 }
 
-hipError_t merge_batched_launch(const uint64_t *partial, const BatchParams *prm, int bucket, int k,
-                                hipStream_t s) {
-  const int chunk = merge_chunk(k, 1 << 20);
+int64_t merge_batched_mid_keys(int bucket, int max_parts, int k) {
+  const int chunk = merge_chunk(k);
+  return static_cast<int64_t>(bucket) * ((max_parts + chunk - 1) / chunk) * k;
+}
+
+hipError_t merge_batched_launch(const uint64_t *partial, const BatchParams *prm, int bucket, int k, int max_parts,
+                                uint64_t *mid, hipStream_t s) {
+  const int chunk = merge_chunk(k);
   if (chunk * k > kMergeLdsKeys) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(merge_lists_kernel, dim3(bucket), dim3(kMergeBlock), 0, s, partial, 0, k, chunk,
-                     static_cast<int32_t *>(nullptr), static_cast<int32_t *>(nullptr), prm);
+  const int gmax = (max_parts + chunk - 1) / chunk;
+  hipLaunchKernelGGL(merge_groups_kernel, dim3(bucket, gmax), dim3(kMergeBlock), 0, s, partial, 0, k, chunk, gmax,
+                     prm, mid);
+  hipLaunchKernelGGL(merge_lists_kernel, dim3(bucket), dim3(kMergeBlock), 0, s, static_cast<const uint64_t *>(mid), 0,
+                     gmax, k, chunk, static_cast<int32_t *>(nullptr), static_cast<int32_t *>(nullptr), prm, chunk);
   return hipGetLastError();
 }
 

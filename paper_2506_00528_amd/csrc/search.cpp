@@ -23,10 +23,12 @@ int search_plain(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids,
   const int G = grid > 0 ? grid : default_plain_grid(db);
   const size_t per_query = static_cast<size_t>(G) * k * sizeof(uint64_t);
   const int chunk = static_cast<int>(std::max<size_t>(1, std::min<size_t>(nq, kPartialBudget / per_query)));
+  const size_t mid_keys = static_cast<size_t>(tqi::merge_mid_keys(chunk, G, k));
   void *p = nullptr;
-  int rc = scratch_get(db->scratch, s, per_query * chunk, &p);
+  int rc = scratch_get(db->scratch, s, per_query * chunk + mid_keys * sizeof(uint64_t), &p);
   if (rc) return rc;
   uint64_t *partial = static_cast<uint64_t *>(p);
+  uint64_t *mid = partial + static_cast<size_t>(chunk) * G * k;
   const int row_words = 2 * db->dev.W;
   for (int q0 = 0; q0 < nq; q0 += chunk) {
     const int nc = std::min(chunk, nq - q0);
@@ -37,7 +39,7 @@ int search_plain(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids,
       if (e != hipSuccess) return hip_fail(e, "plain scan launch");
     }
     hipError_t e = tqi::merge_launch(partial, nc, G, k, ids + static_cast<int64_t>(q0) * k,
-                                     scores + static_cast<int64_t>(q0) * k, s);
+                                     scores + static_cast<int64_t>(q0) * k, mid, s);
     if (e != hipSuccess) return hip_fail(e, "merge launch");
   }
   return TQ_OK;

@@ -93,9 +93,11 @@ struct tq_server {
   uint32_t *d_qtick = nullptr;   // max_slots x 8 nc, the active rows of a tick, compact
   uint64_t *d_running = nullptr; // max_slots x k_run
   uint64_t *d_partial = nullptr; // (qtile * grid + max_slots) x k_run
+  uint64_t *d_mid = nullptr;     // first-stage merge results
+  char *d_tick = nullptr;        // [BatchParams][slots: max_slots ints][retire: max_slots ints]
   tqi::BatchParams *d_prm = nullptr;
-  int *d_slots = nullptr;        // max_slots
-  int *d_retire = nullptr;       // max_slots
+  int *d_slots = nullptr;
+  int *d_retire = nullptr;
   int32_t *d_ids = nullptr, *d_scores = nullptr;  // max_slots x k_run
   // pinned host
   uint32_t *h_qcanon = nullptr;
@@ -160,6 +162,7 @@ struct Admitted {
 };
 
 struct TickPlan {
+  int k = 1;                   // largest k of the active requests
   std::vector<Admitted> admitted;
   std::vector<int> slots;      // rows of every active query
   std::vector<int> retire;     // rows of queries that retire after this tick
@@ -193,24 +196,24 @@ hipError_t enqueue_tick(tq_server *s, TickPlan &p, TickStage &st) {
   }
   const int nq = static_cast<int>(p.slots.size());
   const int nret = static_cast<int>(p.retire.size());
+  const int kt = p.k;  // the tick's k: the largest k of the active requests
+  const int qtile = std::min(s->qtile, tqi::batched_max_qtile(kt));
   tqi::BatchParams b;
   const int64_t lo = p.seg * s->seg_tiles;
   const int64_t hi = std::min<int64_t>(db.ntiles, lo + s->seg_tiles);
-  tqi::batch_split(b, nq, s->qtile, s->grid, lo, hi);
+  tqi::batch_split(b, nq, qtile, s->grid, lo, hi);
   b.slots = s->d_slots;
   b.running = s->d_running;
+  b.running_stride = s->k_run;
   b.ids = nullptr;
   b.scores = nullptr;
   const size_t max_slots = s->slot_used.size();
   std::memcpy(st.host, &b, sizeof b);
   std::memcpy(st.host + sizeof b, p.slots.data(), nq * sizeof(int));
   std::memcpy(st.host + sizeof b + max_slots * sizeof(int), p.retire.data(), nret * sizeof(int));
-  e = hipMemcpyAsync(s->d_prm, st.host, sizeof b, hipMemcpyHostToDevice, s->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(s->d_slots, st.host + sizeof b, nq * sizeof(int), hipMemcpyHostToDevice, s->stream);
-  if (e == hipSuccess && nret)
-    e = hipMemcpyAsync(s->d_retire, st.host + sizeof b + max_slots * sizeof(int), nret * sizeof(int),
-                       hipMemcpyHostToDevice, s->stream);
+  // one copy: parameters, active slots and (up to the used part) retiring slots
+  const size_t span = sizeof b + (nret ? max_slots + nret : static_cast<size_t>(nq)) * sizeof(int);
+  e = hipMemcpyAsync(s->d_tick, st.host, span, hipMemcpyHostToDevice, s->stream);
   if (e == hipSuccess) e = hipEventRecord(st.consumed, s->stream);
   if (e != hipSuccess) return e;
   st.used = true;
@@ -219,10 +222,10 @@ hipError_t enqueue_tick(tq_server *s, TickPlan &p, TickStage &st) {
   if (e != hipSuccess) return e;
   {
     TimedLaunch t(kTimeBatched, s->stream);
-    e = tqi::scan_batched_launch(db, s->d_qtick, s->d_prm, s->k_run, s->qtile, s->grid, s->d_partial, s->stream);
+    e = tqi::scan_batched_launch(db, s->d_qtick, s->d_prm, kt, qtile, s->grid, s->d_partial, s->stream);
   }
   if (e != hipSuccess) return e;
-  e = tqi::merge_batched_launch(s->d_partial, s->d_prm, nq, s->k_run, s->stream);
+  e = tqi::merge_batched_launch(s->d_partial, s->d_prm, nq, kt, s->grid, s->d_mid, s->stream);
   if (e != hipSuccess) return e;
   // retiring requests: results to pinned host memory
   if (nret) {
@@ -328,6 +331,7 @@ void serve_loop(tq_server *s) {
     }
     plan.seg = s->tick % s->S;
     for (Request *r : s->active) {
+      plan.k = std::max(plan.k, r->k);
       for (int qi = 0; qi < r->nq; ++qi) plan.slots.push_back(r->slot0 + qi);
       if (r->ticks_done + 1 == s->S) {
         for (int qi = 0; qi < r->nq; ++qi) plan.retire.push_back(r->slot0 + qi);
@@ -369,7 +373,7 @@ void serve_loop(tq_server *s) {
 void free_server(tq_server *s) {
   if (s->stream) (void)hipStreamSynchronize(s->stream);
   for (void *p : {(void *)s->d_qcanon, (void *)s->d_qrows, (void *)s->d_qtick, (void *)s->d_running, (void *)s->d_partial,
-                  (void *)s->d_prm, (void *)s->d_slots, (void *)s->d_retire, (void *)s->d_ids, (void *)s->d_scores})
+                  (void *)s->d_mid, (void *)s->d_tick, (void *)s->d_ids, (void *)s->d_scores})
     if (p) (void)hipFree(p);
   for (void *p : {(void *)s->h_qcanon, (void *)s->h_ids, (void *)s->h_scores})
     if (p) (void)hipHostFree(p);
@@ -417,7 +421,9 @@ int tq_serve_create(const tq_db *db, const tq_serve_cfg *cfg, tq_server **out) {
   s->grid = (db->num_cu > 0 ? db->num_cu : 256) * 2;
   const int64_t ntiles = db->dev.ntiles;
   int S = c.n_segments;
-  if (S == 0) S = static_cast<int>(std::min<int64_t>(64, std::max<int64_t>(1, (db->dev.n + (1 << 20) - 1) >> 20)));
+  // default: one segment per 16M vectors -- a full pass per tick keeps the
+  // per-tick launch and merge overhead small next to the scan
+  if (S == 0) S = static_cast<int>(std::min<int64_t>(64, std::max<int64_t>(1, (db->dev.n + (1 << 24) - 1) >> 24)));
   S = static_cast<int>(std::min<int64_t>(S, ntiles));
   s->seg_tiles = (ntiles + S - 1) / S;
   s->S = static_cast<int>((ntiles + s->seg_tiles - 1) / s->seg_tiles);
@@ -441,9 +447,16 @@ int tq_serve_create(const tq_db *db, const tq_serve_cfg *cfg, tq_server **out) {
   dm((void **)&s->d_qtick, M * 8 * nc * sizeof(uint32_t));
   dm((void **)&s->d_running, M * s->k_run * sizeof(uint64_t));
   dm((void **)&s->d_partial, (static_cast<size_t>(s->qtile) * s->grid + M) * s->k_run * sizeof(uint64_t));
-  dm((void **)&s->d_prm, sizeof(tqi::BatchParams));
-  dm((void **)&s->d_slots, M * sizeof(int));
-  dm((void **)&s->d_retire, M * sizeof(int));
+  int64_t mid_keys = 0;
+  for (int k = 1; k <= s->k_run; ++k)
+    mid_keys = std::max(mid_keys, tqi::merge_batched_mid_keys(static_cast<int>(M), s->grid, k));
+  dm((void **)&s->d_mid, static_cast<size_t>(mid_keys) * sizeof(uint64_t));
+  dm((void **)&s->d_tick, sizeof(tqi::BatchParams) + 2 * M * sizeof(int));
+  if (e == hipSuccess) {
+    s->d_prm = reinterpret_cast<tqi::BatchParams *>(s->d_tick);
+    s->d_slots = reinterpret_cast<int *>(s->d_tick + sizeof(tqi::BatchParams));
+    s->d_retire = s->d_slots + M;
+  }
   dm((void **)&s->d_ids, M * s->k_run * sizeof(int32_t));
   dm((void **)&s->d_scores, M * s->k_run * sizeof(int32_t));
   hm((void **)&s->h_qcanon, M * 2 * W * sizeof(uint32_t));

@@ -20,8 +20,9 @@ struct BatchParams {
   const int *slots;        // optional: query i's running list is row slots[i] of
                            // `running` (else row i); the scan always reads query
                            // rows compactly (row i for query i)
-  uint64_t *running;       // optional: per-row running top-k (k keys) merged with
-                           // this pass and written back instead of ids / scores
+  uint64_t *running;       // optional: per-row running top-k merged with this
+                           // pass and written back instead of ids / scores
+  int64_t running_stride;  // keys per running row (>= the call's k)
   int32_t *ids;            // caller's outputs, nq x k (when running is null)
   int32_t *scores;
 };
@@ -36,6 +37,7 @@ __host__ __device__ inline void batch_split(BatchParams &b, int nq, int qtile, i
   if (parts < 1) parts = 1;
   b.parts = static_cast<int>(parts);
   b.pad = 0;
+  b.running_stride = 0;
   b.tiles_per_part = (ntiles + parts - 1) / parts;
   b.tile_lo = lo;
   b.tile_hi = hi;
@@ -49,11 +51,12 @@ hipError_t batch_prep_launch(const uint32_t *qcodes, int nq, int bucket, const D
 hipError_t scan_batched_launch(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile,
                                int grid, uint64_t *partial, hipStream_t s);
 // Per-query merge of the (query, part) lists; the query count, part count and
-// output pointers come from `prm`; `bucket` workgroups are launched.  With
+// output pointers come from `prm`; at most max_parts parts per query.  With
 // prm->running set, each query's running list joins the merge and receives
-// the result.
-hipError_t merge_batched_launch(const uint64_t *partial, const BatchParams *prm, int bucket, int k,
-                                hipStream_t s);
+// the result.  `mid` holds merge_batched_mid_keys(bucket, max_parts, k) keys.
+int64_t merge_batched_mid_keys(int bucket, int max_parts, int k);
+hipError_t merge_batched_launch(const uint64_t *partial, const BatchParams *prm, int bucket, int k, int max_parts,
+                                uint64_t *mid, hipStream_t s);
 
 // Canonical query codes -> nz/ng rows (the layout the batched scan reads).
 hipError_t prep_rows_launch(const uint32_t *qcodes, int nq, const DbDev &db, uint32_t *rows, hipStream_t s);

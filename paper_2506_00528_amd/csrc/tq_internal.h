@@ -21,7 +21,7 @@ namespace tqi {
 //   * the planes are stored as nz = v+ | v- (the non-zero mask) and
 //     ng = v- (the negative mask), a lossless re-coding of (v+, v-) that
 //     lets Delta be evaluated with 5 integer operations per 32 coordinates
-//     (see delta_chunk below);
+//     (see delta_word in tq_device.h);
 //   * within a tile, chunk c of plane p of all 64 vectors is one contiguous
 //     1 KiB run: uint4 index ((tile * 2 + p) * nc + c) * 64 + lane.
 //
@@ -86,9 +86,11 @@ hipError_t validate_launch(const uint32_t *codes, int64_t n, int d, int x,
 hipError_t scan_plain_launch(const DbDev &db, const uint32_t *qcode, int k, int grid,
                              uint64_t *partial, hipStream_t s);
 // For each of nq queries, merge its `nlists` sorted lists of k keys (laid out
-// partial[(q * nlists + l) * k + i]) into the final ids / scores.
+// partial[(q * nlists + l) * k + i]) into the final ids / scores.  `mid`
+// holds merge_mid_keys(nq, nlists, k) keys of scratch (may be null when 0).
+int64_t merge_mid_keys(int nq, int nlists, int k);
 hipError_t merge_launch(const uint64_t *partial, int nq, int nlists, int k, int32_t *ids,
-                        int32_t *scores, hipStream_t s);
+                        int32_t *scores, uint64_t *mid, hipStream_t s);
 hipError_t delta_dump_launch(const DbDev &db, const uint32_t *qcodes, int nq, int32_t *out,
                              hipStream_t s);
 
