@@ -1,0 +1,133 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py
+times (default grid and shapes).
+
+mid (N = 1e6, d = 768, x in {96, 192, 384}): every code against the oracle's,
+and top-100 of sampled queries (plain and batched) against the oracle's
+exhaustive search over the oracle's own codes.
+
+large (N = 1e7, d = 1024, x = 256): the oracle cannot encode all 10^7 rows in a
+test's time, so codes are compared on sampled chunks, and each sampled
+query's top-10 is checked by properties that hold at any size: every returned
+score equals the oracle's Delta for that (query, row); results are ordered
+(Delta desc, id asc); and no row of the sampled chunks that is not in the
+result beats the k-th result.  Plain and batched results must be identical.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from tests.libtq import ensure_built
+from workloads import datagen
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stderr.flush()
+
+
+@pytest.fixture(scope="module")
+def tq():
+    return ensure_built()
+
+
+@pytest.fixture(scope="module")
+def o():
+    return oracle.default()
+
+
+def key_of(score, idx):
+    return (int(score), -int(idx))
+
+
+@pytest.fixture(scope="module")
+def mid_data():
+    w = datagen.WORKLOADS["mid"]
+    dev = torch.device("cuda", 0)
+    X = datagen.rows(w["spec"], datagen.DB, 0, w["n"], dev)
+    Q = datagen.rows(w["spec"], datagen.QUERIES, 0, 16, dev)
+    return w, X, Q, X.cpu().numpy(), Q.cpu().numpy()
+
+
+@pytest.mark.parametrize("x", [96, 192, 384])
+def test_mid_full_parity(tq, o, mid_data, x):
+    w, X, Q, Xh, Qh = mid_data
+    d, k = w["d"], w["k"]
+    say(f"mid full size: encode N={w['n']} d={d} x={x}")
+    codes = tq.tq_encode(X, x)
+    qcodes = tq.tq_encode(Q, x)
+    tq.tq_sync()
+    V = o.encode(Xh, x)
+    assert np.array_equal(codes.cpu().numpy().view(np.uint32), o.pack(V)), "codes differ"
+    VQ = o.encode(Qh, x)
+    ei, es = o.knn(VQ, V, k)
+    db = tq.tq_db_create(codes, d, x)
+    del codes
+    for path in (tq.TQ_PATH_PLAIN, tq.TQ_PATH_BATCHED):
+        say(f"mid full size: top-{k} x={x} path={path}")
+        ids, sc = tq.tq_search_knn(db, qcodes, k, path=path)
+        torch.cuda.synchronize()
+        assert np.array_equal(sc.cpu().numpy(), es) and np.array_equal(ids.cpu().numpy(), ei), path
+    db.destroy()
+
+
+def test_large_sampled(tq, o):
+    w = datagen.WORKLOADS["large"]
+    n, d, x, k = w["n"], w["d"], w["x"], w["k"]
+    dev = torch.device("cuda", 0)
+    W = tq.tq_code_words(d)
+    nchunks = (n + datagen.CHUNK - 1) // datagen.CHUNK
+    sample_chunks = [0, 47, 101, nchunks - 1]
+    say(f"large full size: generate + encode N={n} d={d} x={x}")
+    codes = torch.empty((n, 2 * W), dtype=torch.int32, device=dev)
+    sampled = {}
+    for r0, Xc in datagen.iter_rows(w["spec"], datagen.DB, 0, n, dev):
+        tq.tq_encode(Xc, x, codes[r0:r0 + Xc.shape[0]])
+        if r0 // datagen.CHUNK in sample_chunks:
+            sampled[r0] = Xc.cpu().numpy()
+    Q = datagen.rows(w["spec"], datagen.QUERIES, 0, 4, dev)
+    qcodes = tq.tq_encode(Q, x)
+    tq.tq_sync()
+    say("large full size: sampled codes against the oracle")
+    oracle_rows = {}
+    for r0, Xh in sampled.items():
+        V = o.encode(Xh, x)
+        oracle_rows[r0] = V
+        assert np.array_equal(codes[r0:r0 + Xh.shape[0]].cpu().numpy().view(np.uint32), o.pack(V)), r0
+    db = tq.tq_db_create(codes, d, x)
+    del codes
+    say("large full size: top-10 plain and batched")
+    ip, sp = tq.tq_search_knn(db, qcodes, k, path=tq.TQ_PATH_PLAIN)
+    ib, sb = tq.tq_search_knn(db, qcodes, k, path=tq.TQ_PATH_BATCHED)
+    torch.cuda.synchronize()
+    assert torch.equal(ip, ib) and torch.equal(sp, sb), "plain and batched differ"
+    ids, scores = ip.cpu().numpy(), sp.cpu().numpy()
+    VQ = o.encode(Q.cpu().numpy(), x)
+    # every returned score is the oracle's Delta for that row
+    need = sorted(set(ids.ravel().tolist()))
+    rows = torch.empty((len(need), d), dtype=torch.float32)
+    for j, r in enumerate(need):
+        c = r // datagen.CHUNK
+        blk = datagen.chunk(datagen.SPECS[w["spec"]], datagen.DB, c, dev)
+        rows[j] = blk[r - c * datagen.CHUNK].cpu()
+    VR = o.encode(rows.numpy(), x)
+    D = o.delta(VQ, VR)
+    pos = {r: j for j, r in enumerate(need)}
+    for q in range(4):
+        for j in range(k):
+            assert scores[q, j] == D[q, pos[ids[q, j]]], (q, j)
+        keys = [key_of(scores[q, j], ids[q, j]) for j in range(k)]
+        assert keys == sorted(keys, reverse=True), "not ordered"
+        kth = keys[-1]
+        chosen = set(ids[q].tolist())
+        for r0, V in oracle_rows.items():
+            Ds = o.delta(VQ[q:q + 1], V)[0]
+            for i in np.nonzero(Ds >= kth[0])[0]:
+                rid = r0 + int(i)
+                if rid not in chosen:
+                    assert key_of(Ds[i], rid) < kth, f"row {rid} beats the k-th result of query {q}"
+    db.destroy()
