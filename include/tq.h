@@ -162,8 +162,17 @@ typedef struct tq_search_opts {
   int use_graph;     /* batched path: 1 = replay a captured hipGraph for the
                         batch-size bucket (default when the struct is NULL),
                         0 = launch the kernels directly */
-  int reserved[3];
+  int engine;        /* batched path: TQ_ENGINE_AUTO, TQ_ENGINE_POPCOUNT or
+                        TQ_ENGINE_MATRIX (results are identical) */
+  int reserved[2];
 } tq_search_opts;
+
+enum tq_engine {
+  TQ_ENGINE_AUTO = 0,     /* the tuned / default choice */
+  TQ_ENGINE_POPCOUNT = 1, /* Delta by AND / XOR / popcount on the vector ALUs */
+  TQ_ENGINE_MATRIX = 2    /* Delta as a ternary matrix product on the fp4 matrix
+                             cores (exact; k <= 128, query tiles of 16 or 32) */
+};
 
 /* k nearest database codes of each of nq query codes.
  *

@@ -21,7 +21,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libtq.so")
 ARCH = os.environ.get("TQ_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["encode.hip", "layout.hip", "scan.hip", "batched_kernels.hip", "api.cpp", "search.cpp",
+SOURCES = ["encode.hip", "layout.hip", "scan.hip", "batched_kernels.hip", "mfma_kernels.hip", "api.cpp", "search.cpp",
            "batched.cpp", "serve.cpp"]
 
 CFLAGS = [

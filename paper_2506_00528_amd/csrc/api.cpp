@@ -350,6 +350,8 @@ int tq_search_knn(const tq_db *cdb, const uint32_t *qcodes, int nq, int k, int32
   const int path = opts ? opts->path : TQ_PATH_AUTO;
   if (path < TQ_PATH_AUTO || path > TQ_PATH_BATCHED) return fail(TQ_ERR_INVALID, "unknown path %d", path);
   if (opts && (opts->grid < 0 || opts->qtile < 0)) return fail(TQ_ERR_INVALID, "negative grid or qtile");
+  if (opts && (opts->engine < TQ_ENGINE_AUTO || opts->engine > TQ_ENGINE_MATRIX))
+    return fail(TQ_ERR_INVALID, "unknown engine %d", opts->engine);
   DeviceGuard g(db->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   int rc;

@@ -32,6 +32,7 @@ struct Shape {
   int qtile = 0;
   int grid = 0;
   bool plain = false;  // the plain path was faster for this bucket
+  int engine = TQ_ENGINE_POPCOUNT;
 };
 
 // ---------------------------------------------------------------------------
@@ -64,8 +65,8 @@ void tune_load_locked() {
     char key[64];
     Shape s;
     int plain = 0;
-    if (std::sscanf(line, " \"%63[^\"]\": {\"qtile\": %d, \"grid\": %d, \"plain\": %d}", key, &s.qtile, &s.grid,
-                    &plain) == 4) {
+    if (std::sscanf(line, " \"%63[^\"]\": {\"qtile\": %d, \"grid\": %d, \"plain\": %d, \"engine\": %d}", key,
+                    &s.qtile, &s.grid, &plain, &s.engine) == 5) {
       s.plain = plain != 0;
       g_tune.map[key] = s;
     }
@@ -82,8 +83,9 @@ void tune_save_locked() {
   std::fprintf(fp, "{\n");
   size_t i = 0;
   for (auto &kv : g_tune.map) {
-    std::fprintf(fp, " \"%s\": {\"qtile\": %d, \"grid\": %d, \"plain\": %d}%s\n", kv.first.c_str(), kv.second.qtile,
-                 kv.second.grid, kv.second.plain ? 1 : 0, ++i < g_tune.map.size() ? "," : "");
+    std::fprintf(fp, " \"%s\": {\"qtile\": %d, \"grid\": %d, \"plain\": %d, \"engine\": %d}%s\n",
+                 kv.first.c_str(), kv.second.qtile, kv.second.grid, kv.second.plain ? 1 : 0, kv.second.engine,
+                 ++i < g_tune.map.size() ? "," : "");
   }
   std::fprintf(fp, "}\n");
   std::fclose(fp);
@@ -132,7 +134,7 @@ struct BatchEntry {
 
 struct BatchedState {
   hipStream_t capture = nullptr;
-  std::map<std::tuple<hipStream_t, int, int, int, int>, BatchEntry> entries;
+  std::map<std::tuple<hipStream_t, int, int, int, int, int>, BatchEntry> entries;
 };
 
 namespace {
@@ -150,7 +152,7 @@ void free_entry(BatchEntry &e) {
 int get_entry(tq_db *db, hipStream_t s, int bucket, int k, const Shape &sh, BatchEntry **out) {
   if (!db->batched) db->batched = new BatchedState();
   BatchedState &st = *db->batched;
-  auto key = std::make_tuple(s, bucket, k, sh.qtile, sh.grid);
+  auto key = std::make_tuple(s, bucket, k, sh.qtile, sh.grid, sh.engine);
   auto it = st.entries.find(key);
   if (it != st.entries.end()) {
     *out = &it->second;
@@ -158,12 +160,15 @@ int get_entry(tq_db *db, hipStream_t s, int bucket, int k, const Shape &sh, Batc
   }
   BatchEntry e;
   const size_t qbytes = static_cast<size_t>(bucket) * 8 * db->dev.nc * sizeof(uint32_t);
-  const size_t lists = static_cast<size_t>(sh.qtile) * sh.grid + bucket;
+  // (query, part) lists: nq * parts <= qtile * grid + nq, plus up to 7 parts
+  // per query from rounding the part count to a multiple of the XCD count
+  const size_t lists = static_cast<size_t>(sh.qtile) * sh.grid + static_cast<size_t>(tqi::kXcds + 1) * bucket;
   hipError_t err = hipMalloc(&e.qprep, qbytes);
   if (err == hipSuccess) err = hipMalloc(&e.prm, sizeof(tqi::BatchParams));
   if (err == hipSuccess) err = hipMalloc(&e.partial, lists * k * sizeof(uint64_t));
   if (err == hipSuccess)
-    err = hipMalloc(&e.mid, static_cast<size_t>(tqi::merge_batched_mid_keys(bucket, sh.grid, k)) * sizeof(uint64_t));
+    err = hipMalloc(&e.mid, static_cast<size_t>(tqi::merge_batched_mid_keys(bucket, sh.grid + tqi::kXcds, k)) *
+                                sizeof(uint64_t));
   if (err != hipSuccess) {
     free_entry(e);
     return hip_fail(err, "hipMalloc(batched buffers)");
@@ -172,10 +177,16 @@ int get_entry(tq_db *db, hipStream_t s, int bucket, int k, const Shape &sh, Batc
   return TQ_OK;
 }
 
+hipError_t launch_scan(tq_db *db, BatchEntry &e, int k, const Shape &sh, hipStream_t s) {
+  if (sh.engine == TQ_ENGINE_MATRIX)
+    return tqi::scan_mfma_launch(db->dev, e.qprep, e.prm, k, sh.qtile, sh.grid, e.partial, s);
+  return tqi::scan_batched_launch(db->dev, e.qprep, e.prm, k, sh.qtile, sh.grid, e.partial, s);
+}
+
 int enqueue_scan_merge(tq_db *db, BatchEntry &e, int bucket, int k, const Shape &sh, hipStream_t s) {
-  hipError_t err = tqi::scan_batched_launch(db->dev, e.qprep, e.prm, k, sh.qtile, sh.grid, e.partial, s);
+  hipError_t err = launch_scan(db, e, k, sh, s);
   if (err != hipSuccess) return hip_fail(err, "batched scan launch");
-  err = tqi::merge_batched_launch(e.partial, e.prm, bucket, k, sh.grid, e.mid, s);
+  err = tqi::merge_batched_launch(e.partial, e.prm, bucket, k, sh.grid + tqi::kXcds, e.mid, s);
   if (err != hipSuccess) return hip_fail(err, "batched merge launch");
   return TQ_OK;
 }
@@ -223,10 +234,10 @@ int run_chunk(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids, in
     // timed runs launch directly so the events bracket the scan kernel alone
     {
       TimedLaunch t(kTimeBatched, s);
-      err = tqi::scan_batched_launch(db->dev, e->qprep, e->prm, k, sh.qtile, sh.grid, e->partial, s);
+      err = launch_scan(db, *e, k, sh, s);
     }
     if (err != hipSuccess) return hip_fail(err, "batched scan launch");
-    err = tqi::merge_batched_launch(e->partial, e->prm, bucket, k, sh.grid, e->mid, s);
+    err = tqi::merge_batched_launch(e->partial, e->prm, bucket, k, sh.grid + tqi::kXcds, e->mid, s);
     if (err != hipSuccess) return hip_fail(err, "batched merge launch");
     return TQ_OK;
   }
@@ -242,6 +253,11 @@ int run_chunk(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids, in
 Shape shape_for(tq_db *db, int k, int bucket, const tq_search_opts *opts) {
   Shape sh;
   if (!tune_lookup(db->dev.nc, k, bucket, &sh)) sh = default_shape(db, k, bucket);
+  if (opts && opts->engine != TQ_ENGINE_AUTO && opts->engine != sh.engine) {
+    sh.engine = opts->engine;
+    if (sh.engine == TQ_ENGINE_MATRIX) sh.qtile = bucket > 64 ? 128 : 64;
+    else sh.qtile = default_shape(db, k, bucket).qtile;
+  }
   if (opts && opts->qtile > 0) sh.qtile = opts->qtile;
   if (opts && opts->grid > 0) sh.grid = opts->grid;
   return sh;
@@ -260,11 +276,19 @@ int choose_path(tq_db *db, int requested, int nq, int k) {
 int search_batched(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids, int32_t *scores,
                    const tq_search_opts *opts, hipStream_t s) {
   const bool use_graph = opts ? opts->use_graph != 0 : true;
+  const int engine = opts ? opts->engine : TQ_ENGINE_AUTO;
+  if (engine < TQ_ENGINE_AUTO || engine > TQ_ENGINE_MATRIX) return fail(TQ_ERR_INVALID, "unknown engine %d", engine);
+  if (engine == TQ_ENGINE_MATRIX && tqi::rows_for_k(k) > 2)
+    return fail(TQ_ERR_INVALID, "the matrix engine supports k <= 128 (k=%d)", k);
   if (opts && opts->qtile > 0) {
     const int q = opts->qtile;
-    if (q != 2 && q != 4 && q != 8 && q != 16) return fail(TQ_ERR_INVALID, "qtile=%d is not 2, 4, 8 or 16", q);
-    if (q > tqi::batched_max_qtile(k))
-      return fail(TQ_ERR_INVALID, "qtile=%d exceeds %d for k=%d", q, tqi::batched_max_qtile(k), k);
+    if (engine == TQ_ENGINE_MATRIX) {
+      if (q != 64 && q != 128) return fail(TQ_ERR_INVALID, "matrix engine: qtile=%d is not 64 or 128", q);
+    } else {
+      if (q != 2 && q != 4 && q != 8 && q != 16) return fail(TQ_ERR_INVALID, "qtile=%d is not 2, 4, 8 or 16", q);
+      if (q > tqi::batched_max_qtile(k))
+        return fail(TQ_ERR_INVALID, "qtile=%d exceeds %d for k=%d", q, tqi::batched_max_qtile(k), k);
+    }
   }
   const int row_words = 2 * db->dev.W;
   for (int q0 = 0; q0 < nq; q0 += kMaxBucket) {
@@ -361,6 +385,18 @@ int autotune(tq_db *db, int nq_max, const int *ks, int nks, hipStream_t s, int v
           cands.push_back(c);
         }
       }
+      if (tqi::rows_for_k(k) <= 2) {
+        for (int qt : {64, 128}) {
+          if (qt > 64 && b <= 64) continue;
+          for (int gm : {2, 4}) {
+            Shape c;
+            c.engine = TQ_ENGINE_MATRIX;
+            c.qtile = qt;
+            c.grid = cu * gm;
+            cands.push_back(c);
+          }
+        }
+      }
       Shape best;
       float best_ms = 1e30f;
       for (const Shape &c : cands) {
@@ -369,7 +405,7 @@ int autotune(tq_db *db, int nq_max, const int *ks, int nks, hipStream_t s, int v
         if (rc) break;
         if (verbose)
           std::fprintf(stderr, "[tq tune] k=%d bucket=%d %s qtile=%d grid=%d: %.3f ms\n", k, b,
-                       c.plain ? "plain" : "batched", c.qtile, c.grid, ms);
+                       c.plain ? "plain" : c.engine == TQ_ENGINE_MATRIX ? "matrix" : "popcount", c.qtile, c.grid, ms);
         if (ms < best_ms) {
           best_ms = ms;
           best = c;
@@ -380,6 +416,7 @@ int autotune(tq_db *db, int nq_max, const int *ks, int nks, hipStream_t s, int v
           Shape d = default_shape(db, k, b);
           best.qtile = d.qtile;
           best.grid = d.grid;
+          best.engine = d.engine;
         }
         tune_store(db->dev.nc, k, b, best);
       }

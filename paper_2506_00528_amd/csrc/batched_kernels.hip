@@ -115,8 +115,8 @@ __global__ __launch_bounds__(kBatchBlock) void scan_batched_kernel(const uint4 *
   const int km1 = k - 1;
 
   for (int item = blockIdx.x; item < items; item += gridDim.x) {
-    const int qt = item % nqt;
-    const int part = item / nqt;
+    int qt, part;
+    item_coords(item, nqt, &qt, &part);
     const int q0 = qt * QT;
     const int nact = min(QT, nq - q0);
     const int64_t t0 = tile_lo + static_cast<int64_t>(part) * tpp;

@@ -1,0 +1,278 @@
+// mfma_kernels.hip -- the batched scan on the matrix cores.
+//
+// When one database pass serves many queries, Delta for all (query, vector)
+// pairs is exactly the product of two ternary matrices (the scalar products
+// of Sec. 5.1.2).  {-1, 0, +1} are exact fp4 (e2m1) values and every partial
+// sum (at most d <= 1024 in magnitude) is exact in fp32, so the gfx950 fp4
+// MFMA V_MFMA_SCALE_F32_16X16X128_F8F6F4 (scales 2^0) gives the same integers
+// as the popcount form, at several times its rate.
+//
+// Operand re-coding.  A product over k is unchanged by any permutation of k
+// applied to both operands, so one 32-coordinate word of the nz / ng planes
+// becomes 32 fp4 operand values without spreading bits: dimension 4j + q of
+// the word becomes nibble j of dword q, with nibble value 0b0010 (+1.0) where
+// nz is set and 0b1010 (-1.0) where ng is set too, i.e.
+//   dword q = ((nz >> (q-1)) & 0x22222222) | ((ng << (3-q)) & 0x88888888).
+// Queries (operand A, 16 rows) and database vectors (operand B, 16 columns)
+// use the same re-coding; lane l supplies row / column l % 16 and the word
+// 4s + l / 16 of K-step s (128 coordinates, one 16-byte chunk of a plane).
+//
+// Work: a persistent grid walks (query tile, database part) items like the
+// popcount kernel, but here a workgroup's four waves each own 16*RB queries
+// of the tile (64*RB per tile) and all four sweep the same database tiles.
+// Each 64-vector tile is read from HBM once per workgroup, re-coded to fp4
+// operands by the whole workgroup while it is staged into LDS (double
+// buffered: the next tile's loads are in flight while the current one is
+// multiplied), and read by every wave from LDS.  A wave accumulates a
+// 16*RB x 64 block of Delta in fp32, compares each value with its row's
+// current k-th score (a float kept per lane), and only on the rare candidates
+// builds exact keys and inserts them, in id order, into its register top-k
+// list for that query.  A query belongs to one wave, so a wave's list is the
+// (query, part) result and no merge inside the workgroup is needed.
+#include "tq_batched.h"
+#include "tq_device.h"
+
+namespace tqi {
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kMfmaWaves = 4;
+constexpr int kMfmaBlock = 64 * kMfmaWaves;
+constexpr int kScaleOne = 0x7f7f7f7f;  // e8m0 exponent 127 in every byte: scale 2^0
+
+// 32 coordinates (one word of each plane) -> 32 fp4 operand values (16 bytes).
+__device__ __forceinline__ v4i fp4_operand(uint32_t nz, uint32_t ng) {
+  const uint32_t d0 = ((nz << 1) & 0x22222222u) | ((ng << 3) & 0x88888888u);
+  const uint32_t d1 = (nz & 0x22222222u) | ((ng << 2) & 0x88888888u);
+  const uint32_t d2 = ((nz >> 1) & 0x22222222u) | ((ng << 1) & 0x88888888u);
+  const uint32_t d3 = ((nz >> 2) & 0x22222222u) | (ng & 0x88888888u);
+  v4i r = {static_cast<int>(d0), static_cast<int>(d1), static_cast<int>(d2), static_cast<int>(d3)};
+  return r;
+}
+
+// fp4 operands use the low four dwords of the instruction's eight.
+__device__ __forceinline__ v4f mfma_fp4(const v4i &a, const v4i &b, const v4f &c) {
+  const v8i a8 = {a.x, a.y, a.z, a.w, 0, 0, 0, 0};
+  const v8i b8 = {b.x, b.y, b.z, b.w, 0, 0, 0, 0};
+  return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a8, b8, c, 4, 4, 0, kScaleOne, 0, kScaleOne);
+}
+
+__device__ __forceinline__ float score_of(uint64_t thr) {
+  // the k-th key's score as a float; an empty slot lets everything through
+  return thr ? static_cast<float>(key_score(thr)) : -1e30f;
+}
+
+// Staging of one 64-vector tile: thread j re-codes the words that lane j % 64
+// of every wave reads for column block (j / 64) at each K-step, i.e. word
+// 4s + (j % 64) / 16 of vector 16 (j / 64) + j % 16, for s = 0 .. NC-1.
+template <int NC>
+struct TileStage {
+  uint32_t nz[NC], ng[NC];
+
+  __device__ __forceinline__ void load(const uint32_t *__restrict__ words, int64_t t, int j) {
+    const int lane = j & 63, cb = j >> 6;
+    const int v = cb * 16 + (lane & 15), grp = lane >> 4;
+#pragma unroll
+    for (int s = 0; s < NC; ++s) {
+      const int64_t i0 = ((t * 2 + 0) * NC + s) * 64 + v;
+      const int64_t i1 = ((t * 2 + 1) * NC + s) * 64 + v;
+      nz[s] = __builtin_nontemporal_load(words + i0 * 4 + grp);
+      ng[s] = __builtin_nontemporal_load(words + i1 * 4 + grp);
+    }
+  }
+  // operand (s, cb) of lane l lives at op[(s * 4 + cb) * 64 + l]
+  __device__ __forceinline__ void store(v4i *op, int j) const {
+#pragma unroll
+    for (int s = 0; s < NC; ++s) op[s * 256 + j] = fp4_operand(nz[s], ng[s]);
+  }
+};
+
+template <int NC, int R, int RB>
+__global__ __launch_bounds__(kMfmaBlock) void scan_mfma_kernel(const uint4 *__restrict__ tiles, int64_t n,
+                                                              const uint32_t *__restrict__ qprep,
+                                                              const BatchParams *__restrict__ prm, int k,
+                                                              uint64_t *__restrict__ partial) {
+  constexpr int QW = 16 * RB;            // queries per wave
+  constexpr int QT = kMfmaWaves * QW;    // queries per workgroup tile
+  __shared__ v4i op[2][NC * 4 * 64];     // two staged tiles of fp4 operands
+  const int j = threadIdx.x;
+  const int lane = j & 63;
+  const int wave = j >> 6;
+  const int col = lane & 15;  // operand row / column of this lane
+  const int grp = lane >> 4;  // k-block of this lane; also its output row group
+  const int nq = prm->nq, nqt = prm->nqt, parts = prm->parts;
+  const int64_t tpp = prm->tiles_per_part;
+  const int64_t tile_lo = prm->tile_lo, tile_hi = prm->tile_hi;
+  const int items = nqt * parts;
+  const int km1 = k - 1;
+  const uint32_t *words = reinterpret_cast<const uint32_t *>(tiles);
+
+  for (int item = blockIdx.x; item < items; item += gridDim.x) {
+    int qt, part;
+    item_coords(item, nqt, &qt, &part);
+    const int q0 = qt * QT + wave * QW;  // this wave's first query
+    const int nact = max(0, min(QW, nq - q0));
+    const int64_t t0 = tile_lo + static_cast<int64_t>(part) * tpp;
+    const int64_t t1 = min(tile_hi, t0 + tpp);
+
+    // operand A: this wave's queries, re-coded once per item
+    v4i a[RB][NC];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      const int qi = rb * 16 + col;
+      const uint32_t *qw = qprep + static_cast<int64_t>(q0 + qi) * (8 * NC);
+#pragma unroll
+      for (int s = 0; s < NC; ++s) {
+        uint32_t nz = 0, ng = 0;
+        if (qi < nact) {
+          nz = qw[4 * s + grp];
+          ng = qw[4 * NC + 4 * s + grp];
+        }
+        a[rb][s] = fp4_operand(nz, ng);
+      }
+    }
+    WaveList<R> list[QW];
+#pragma unroll
+    for (int qi = 0; qi < QW; ++qi) list[qi].clear();
+    // tv[rb][i]: k-th score of this lane's output row 16 rb + 4 grp + i;
+    // rows past the real queries never pass
+    float tv[RB][4];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) tv[rb][i] = (rb * 16 + 4 * grp + i < nact) ? -1e30f : 1e30f;
+
+    TileStage<NC> stage;
+    if (t0 < t1) {
+      stage.load(words, t0, j);
+      stage.store(op[0], j);
+    }
+    __syncthreads();
+    for (int64_t t = t0; t < t1; ++t) {
+      const int buf = static_cast<int>((t - t0) & 1);
+      const bool more = t + 1 < t1;
+      if (more) stage.load(words, t + 1, j);  // in flight during the products
+
+      if (nact > 0) {
+        v4f acc[RB][4];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb) {
+            const v4i b = op[buf][(s * 4 + cb) * 64 + lane];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) acc[rb][cb] = mfma_fp4(a[rb][s], b, acc[rb][cb]);
+          }
+        }
+        // rows with a value above their k-th score (rare once lists are full)
+        uint64_t rows[RB][4];
+        bool any = false;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            bool c = false;
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) c |= acc[rb][cb][i] > tv[rb][i];
+            rows[rb][i] = __ballot(c);
+            any |= rows[rb][i] != 0;
+          }
+        if (any) {
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              if (!rows[rb][i]) continue;
+#pragma unroll
+              for (int g = 0; g < 4; ++g) {
+                // lanes of group g carry row 16 rb + 4 g + i
+                const int qi = rb * 16 + 4 * g + i;
+                if (!(rows[rb][i] & (0xFFFFull << (16 * g))) || qi >= nact) continue;
+                uint64_t thr = list[qi].at(km1);
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) {  // increasing ids
+                  const int64_t id = t * 64 + cb * 16 + col;
+                  const float v = acc[rb][cb][i];
+                  const uint64_t key = make_key(static_cast<int32_t>(v), static_cast<uint32_t>(id));
+                  uint64_t m = __ballot(grp == g && id < n && key > thr) ;
+                  while (m) {
+                    const int src = __builtin_ctzll(m);
+                    m &= m - 1;
+                    const uint64_t c = readlane64(key, src);
+                    if (c > thr) {
+                      list[qi].insert(c, lane);
+                      thr = list[qi].at(km1);
+                    }
+                  }
+                }
+                if (grp == g) tv[rb][i] = score_of(thr);
+              }
+            }
+          }
+        }
+      }
+      if (more) stage.store(op[buf ^ 1], j);
+      __syncthreads();
+    }
+
+    // a query belongs to one wave: its list is the (query, part) result
+#pragma unroll
+    for (int qi = 0; qi < QW; ++qi) {
+      if (qi < nact) {
+        uint64_t *dst = partial + (static_cast<int64_t>(q0 + qi) * parts + part) * k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int p = r * 64 + lane;
+          if (p < k) dst[p] = list[qi].v[r];
+        }
+      }
+    }
+  }
+}
+
+template <int NC, int R, int RB>
+hipError_t launch_m3(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int grid,
+                     uint64_t *partial, hipStream_t s) {
+  hipLaunchKernelGGL((scan_mfma_kernel<NC, R, RB>), dim3(grid), dim3(kMfmaBlock), 0, s, db.tiles, db.n, qprep, prm,
+                     k, partial);
+  return hipGetLastError();
+}
+
+template <int NC>
+hipError_t launch_m1(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile, int grid,
+                     uint64_t *partial, hipStream_t s) {
+  const int r = rows_for_k(k);
+  if (qtile == 64) return r == 1 ? launch_m3<NC, 1, 1>(db, qprep, prm, k, grid, partial, s)
+                                 : launch_m3<NC, 2, 1>(db, qprep, prm, k, grid, partial, s);
+  return r == 1 ? launch_m3<NC, 1, 2>(db, qprep, prm, k, grid, partial, s)
+                : launch_m3<NC, 2, 2>(db, qprep, prm, k, grid, partial, s);
+}
+
+}  // namespace
+
+bool mfma_supported(int k, int qtile) { return rows_for_k(k) <= 2 && (qtile == 64 || qtile == 128); }
+
+hipError_t scan_mfma_launch(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile,
+                            int grid, uint64_t *partial, hipStream_t s) {
+  if (!mfma_supported(k, qtile)) return hipErrorInvalidValue;
+  switch (db.nc) {
+    case 1: return launch_m1<1>(db, qprep, prm, k, qtile, grid, partial, s);
+    case 2: return launch_m1<2>(db, qprep, prm, k, qtile, grid, partial, s);
+    case 3: return launch_m1<3>(db, qprep, prm, k, qtile, grid, partial, s);
+    case 4: return launch_m1<4>(db, qprep, prm, k, qtile, grid, partial, s);
+    case 5: return launch_m1<5>(db, qprep, prm, k, qtile, grid, partial, s);
+    case 6: return launch_m1<6>(db, qprep, prm, k, qtile, grid, partial, s);
+    case 7: return launch_m1<7>(db, qprep, prm, k, qtile, grid, partial, s);
+    case 8: return launch_m1<8>(db, qprep, prm, k, qtile, grid, partial, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace tqi

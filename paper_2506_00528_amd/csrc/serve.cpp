@@ -225,7 +225,7 @@ hipError_t enqueue_tick(tq_server *s, TickPlan &p, TickStage &st) {
     e = tqi::scan_batched_launch(db, s->d_qtick, s->d_prm, kt, qtile, s->grid, s->d_partial, s->stream);
   }
   if (e != hipSuccess) return e;
-  e = tqi::merge_batched_launch(s->d_partial, s->d_prm, nq, kt, s->grid, s->d_mid, s->stream);
+  e = tqi::merge_batched_launch(s->d_partial, s->d_prm, nq, kt, s->grid + tqi::kXcds, s->d_mid, s->stream);
   if (e != hipSuccess) return e;
   // retiring requests: results to pinned host memory
   if (nret) {
@@ -446,10 +446,11 @@ int tq_serve_create(const tq_db *db, const tq_serve_cfg *cfg, tq_server **out) {
   dm((void **)&s->d_qrows, M * 8 * nc * sizeof(uint32_t));
   dm((void **)&s->d_qtick, M * 8 * nc * sizeof(uint32_t));
   dm((void **)&s->d_running, M * s->k_run * sizeof(uint64_t));
-  dm((void **)&s->d_partial, (static_cast<size_t>(s->qtile) * s->grid + M) * s->k_run * sizeof(uint64_t));
+  dm((void **)&s->d_partial,
+     (static_cast<size_t>(s->qtile) * s->grid + (tqi::kXcds + 1) * M) * s->k_run * sizeof(uint64_t));
   int64_t mid_keys = 0;
   for (int k = 1; k <= s->k_run; ++k)
-    mid_keys = std::max(mid_keys, tqi::merge_batched_mid_keys(static_cast<int>(M), s->grid, k));
+    mid_keys = std::max(mid_keys, tqi::merge_batched_mid_keys(static_cast<int>(M), s->grid + tqi::kXcds, k));
   dm((void **)&s->d_mid, static_cast<size_t>(mid_keys) * sizeof(uint64_t));
   dm((void **)&s->d_tick, sizeof(tqi::BatchParams) + 2 * M * sizeof(int));
   if (e == hipSuccess) {

@@ -27,7 +27,23 @@ struct BatchParams {
   int32_t *scores;
 };
 
-// Host-side fill of the derived split of a batch over tiles [lo, hi).
+// Work items are (query tile, database part) pairs.  The hardware dispatcher
+// places workgroup b on XCD b mod 8, and a persistent workgroup keeps item
+// indices b, b + grid, ... (grid a multiple of 8), so an item's XCD is its
+// index mod 8.  Items are numbered so that every query tile of a database
+// part runs on the same XCD at about the same time and shares the part's
+// tiles through that XCD's L2: item i -> XCD x = i mod 8, r = i div 8,
+// query tile r mod nqt, part 8 (r div nqt) + x.  The part count is a multiple
+// of 8 (trailing parts may be empty).
+constexpr int kXcds = 8;
+
+__host__ __device__ inline void item_coords(int item, int nqt, int *qt, int *part) {
+  const int x = item % kXcds, r = item / kXcds;
+  *qt = r % nqt;
+  *part = (r / nqt) * kXcds + x;
+}
+
+// Fill of the derived split of a batch over tiles [lo, hi).
 __host__ __device__ inline void batch_split(BatchParams &b, int nq, int qtile, int grid, int64_t lo, int64_t hi) {
   b.nq = nq;
   b.nqt = (nq + qtile - 1) / qtile;
@@ -35,6 +51,7 @@ __host__ __device__ inline void batch_split(BatchParams &b, int nq, int qtile, i
   int64_t parts = b.nqt > 0 ? (grid + b.nqt - 1) / b.nqt : 1;
   if (parts > ntiles) parts = ntiles;
   if (parts < 1) parts = 1;
+  parts = (parts + kXcds - 1) / kXcds * kXcds;
   b.parts = static_cast<int>(parts);
   b.pad = 0;
   b.running_stride = 0;
@@ -50,6 +67,11 @@ hipError_t batch_prep_launch(const uint32_t *qcodes, int nq, int bucket, const D
                              int32_t *ids, int32_t *scores, uint32_t *qprep, BatchParams *prm, hipStream_t s);
 hipError_t scan_batched_launch(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile,
                                int grid, uint64_t *partial, hipStream_t s);
+// The same scan on the fp4 matrix cores (mfma_kernels.hip): k <= 128 and
+// query tiles of 64 or 128 per workgroup.
+bool mfma_supported(int k, int qtile);
+hipError_t scan_mfma_launch(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile,
+                            int grid, uint64_t *partial, hipStream_t s);
 // Per-query merge of the (query, part) lists; the query count, part count and
 // output pointers come from `prm`; at most max_parts parts per query.  With
 // prm->running set, each query's running list joins the merge and receives

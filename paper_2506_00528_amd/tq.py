@@ -31,6 +31,10 @@ TQ_PATH_AUTO = 0
 TQ_PATH_PLAIN = 1
 TQ_PATH_BATCHED = 2
 
+TQ_ENGINE_AUTO = 0
+TQ_ENGINE_POPCOUNT = 1
+TQ_ENGINE_MATRIX = 2
+
 TQ_MAX_D = 1024
 TQ_MAX_K = 512
 
@@ -51,7 +55,8 @@ class TQError(RuntimeError):
 
 class tq_search_opts(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int), ("check_queries", ctypes.c_int), ("grid", ctypes.c_int),
-                ("qtile", ctypes.c_int), ("use_graph", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
+                ("qtile", ctypes.c_int), ("use_graph", ctypes.c_int), ("engine", ctypes.c_int),
+                ("reserved", ctypes.c_int * 2)]
 
 
 class tq_serve_cfg(ctypes.Structure):
@@ -234,15 +239,17 @@ def tq_db_export(db: tq_db, codes: Optional[torch.Tensor] = None, stream=None) -
     return codes
 
 
-def _opts(path=TQ_PATH_AUTO, check_queries=False, grid=0, qtile=0, use_graph=1):
+def _opts(path=TQ_PATH_AUTO, check_queries=False, grid=0, qtile=0, use_graph=1, engine=TQ_ENGINE_AUTO):
     o = tq_search_opts()
     o.path, o.check_queries, o.grid, o.qtile, o.use_graph = int(path), int(bool(check_queries)), int(grid), \
         int(qtile), int(use_graph)
+    o.engine = int(engine)
     return o
 
 
 def tq_search_knn(db: tq_db, qcodes: torch.Tensor, k: int, path: int = TQ_PATH_AUTO, check_queries: bool = False,
-                  grid: int = 0, qtile: int = 0, use_graph: int = 1, ids: Optional[torch.Tensor] = None,
+                  grid: int = 0, qtile: int = 0, use_graph: int = 1, engine: int = TQ_ENGINE_AUTO,
+                  ids: Optional[torch.Tensor] = None,
                   scores: Optional[torch.Tensor] = None, stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
     """Top-k (ids, scores) of every query code, nearest first (Delta desc, id asc)."""
     if qcodes.dim() != 2 or qcodes.shape[1] != 2 * db.W:
@@ -253,7 +260,7 @@ def tq_search_knn(db: tq_db, qcodes: torch.Tensor, k: int, path: int = TQ_PATH_A
             ids = torch.empty((nq, k), dtype=torch.int32, device=db.device)
         if scores is None:
             scores = torch.empty((nq, k), dtype=torch.int32, device=db.device)
-        o = _opts(path, check_queries, grid, qtile, use_graph)
+        o = _opts(path, check_queries, grid, qtile, use_graph, engine)
         _check(lib().tq_search_knn(db.handle, _dev(qcodes, "qcodes", torch.int32), nq, int(k),
                                    _dev(ids, "ids", torch.int32), _dev(scores, "scores", torch.int32),
                                    ctypes.byref(o), _stream(qcodes, stream)), "tq_search_knn")

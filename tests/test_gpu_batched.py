@@ -144,3 +144,89 @@ def test_autotune_then_auto(tq, o, small, tmp_path, monkeypatch):
             ids, sc = run(tq, small["db"], small["CQ"][:nq], k, path=tq.TQ_PATH_AUTO)
             ei, es = o.knn(small["VQ"][:nq], small["V"], k)
             assert np.array_equal(sc, es) and np.array_equal(ids, ei), (nq, k)
+
+
+# ---------------------------------------------------------------------------
+# the matrix-core engine (fp4 MFMA): same results, bit for bit
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("k", [1, 10, 64, 65, 100, 128])
+@pytest.mark.parametrize("nq", [1, 3, 17, 100])
+@pytest.mark.parametrize("qtile", [64, 128])
+def test_matrix_vs_oracle(tq, o, small, k, nq, qtile):
+    say(f"matrix engine small k={k} nq={nq} qtile={qtile}")
+    ids, sc = run(tq, small["db"], small["CQ"][:nq], k, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_MATRIX,
+                  qtile=qtile)
+    ei, es = o.knn(small["VQ"][:nq], small["V"], k)
+    assert np.array_equal(sc, es) and np.array_equal(ids, ei)
+
+
+@pytest.mark.parametrize("grid", [1, 7, 256, 1024])
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_matrix_shapes(tq, o, small, grid, use_graph):
+    say(f"matrix engine grid={grid} graph={use_graph}")
+    ids, sc = run(tq, small["db"], small["CQ"][:200], 10, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_MATRIX,
+                  grid=grid, use_graph=use_graph)
+    ei, es = o.knn(small["VQ"][:200], small["V"], 10)
+    assert np.array_equal(sc, es) and np.array_equal(ids, ei)
+
+
+def test_matrix_many_queries(tq, o, small):
+    say("matrix engine nq=1500")
+    ids, sc = run(tq, small["db"], small["CQ"], 100, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_MATRIX)
+    ei, es = o.knn(small["VQ"], small["V"], 100)
+    assert np.array_equal(sc, es) and np.array_equal(ids, ei)
+
+
+@pytest.mark.parametrize("d", [1, 31, 33, 100, 128, 129, 255, 384, 500, 640, 768, 1000, 1024])
+def test_matrix_dims(tq, o, d):
+    rng = np.random.default_rng(300 + d)
+    n, x, k = 777, max(1, (2 * d) // 3), 20
+    V = o.encode(rng.standard_normal((n, d)).astype(np.float32), x)
+    VQ = o.encode(rng.standard_normal((40, d)).astype(np.float32), x)
+    say(f"matrix engine d={d} n={n} x={x}")
+    db = tq.tq_db_create(dev_codes(o.pack(V)), d, x)
+    ids, sc = run(tq, db, o.pack(VQ), k, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_MATRIX)
+    ei, es = o.knn(VQ, V, k)
+    assert np.array_equal(sc, es) and np.array_equal(ids, ei)
+    db.destroy()
+
+
+def test_matrix_heavy_ties(tq, o):
+    rng = np.random.default_rng(23)
+    d, x = 256, 64
+    base = o.encode(rng.standard_normal((6, d)).astype(np.float32), x)
+    V = base[rng.integers(0, 6, size=20000)]
+    VQ = np.concatenate([base[:3], o.encode(rng.standard_normal((40, d)).astype(np.float32), x)])
+    say("matrix engine heavy ties")
+    db = tq.tq_db_create(dev_codes(o.pack(V)), d, x)
+    for k in (1, 10, 100, 128):
+        ids, sc = run(tq, db, o.pack(VQ), k, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_MATRIX)
+        ei, es = o.knn(VQ, V, k)
+        assert np.array_equal(sc, es) and np.array_equal(ids, ei), k
+    db.destroy()
+
+
+def test_matrix_graph_replays(tq, o, small):
+    rng = np.random.default_rng(4)
+    junk = torch.zeros(1 << 20, device="cuda")
+    for rep in range(5):
+        nq = int(rng.integers(65, 129))
+        q0 = int(rng.integers(0, 1300))
+        say(f"matrix graph replay {rep} nq={nq}")
+        junk.add_(1.0)
+        junk.sum().item()
+        ids, sc = run(tq, small["db"], small["CQ"][q0:q0 + nq], 10, path=tq.TQ_PATH_BATCHED,
+                      engine=tq.TQ_ENGINE_MATRIX)
+        ei, es = o.knn(small["VQ"][q0:q0 + nq], small["V"], 10)
+        assert np.array_equal(sc, es) and np.array_equal(ids, ei), rep
+
+
+def test_matrix_rejects(tq, small):
+    q = dev_codes(small["CQ"][:4])
+    with pytest.raises(tq.TQError):
+        tq.tq_search_knn(small["db"], q, 200, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_MATRIX)
+    with pytest.raises(tq.TQError):
+        tq.tq_search_knn(small["db"], q, 10, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_MATRIX, qtile=16)
+    with pytest.raises(tq.TQError):
+        tq.tq_search_knn(small["db"], q, 10, path=tq.TQ_PATH_BATCHED, engine=7)
