@@ -108,12 +108,31 @@ void tune_store(int nc, int k, int bucket, const Shape &s) {
   tune_save_locked();
 }
 
+}  // namespace
+
+// Untuned choice, from measurements on MI355X (N = 1e7, d = 1024): the
+// matrix engine wins from 16 queries for k <= 64 and from 64 queries for
+// k <= 128; the popcount engine below that and for larger k.
+int default_engine(int k, int nq) {
+  const int r = tqi::rows_for_k(k);
+  if (r == 1 && nq >= 16) return TQ_ENGINE_MATRIX;
+  if (r == 2 && nq >= 64) return TQ_ENGINE_MATRIX;
+  return TQ_ENGINE_POPCOUNT;
+}
+
+namespace {
+
 Shape default_shape(const tq_db *db, int k, int bucket) {
   Shape s;
-  const int qmax = tqi::batched_max_qtile(k);
-  s.qtile = std::min(qmax, bucket <= 2 ? 2 : bucket <= 4 ? 4 : bucket <= 8 ? 8 : 16);
   s.grid = (db->num_cu > 0 ? db->num_cu : 256) * 2;
   s.plain = bucket == 1;
+  s.engine = default_engine(k, bucket);
+  if (s.engine == TQ_ENGINE_MATRIX) {
+    s.qtile = 64;
+  } else {
+    const int qmax = tqi::batched_max_qtile(k);
+    s.qtile = std::min(qmax, bucket <= 2 ? 2 : bucket <= 4 ? 4 : bucket <= 8 ? 8 : 16);
+  }
   return s;
 }
 
@@ -250,15 +269,25 @@ int run_chunk(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids, in
   return enqueue_scan_merge(db, *e, bucket, k, sh, s);
 }
 
+// Engine and query tile of a call: explicit options first, then the tuning
+// cache, then the default.  An explicit query tile implies its engine (2..16:
+// popcount, 64 / 128: matrix).
 Shape shape_for(tq_db *db, int k, int bucket, const tq_search_opts *opts) {
   Shape sh;
   if (!tune_lookup(db->dev.nc, k, bucket, &sh)) sh = default_shape(db, k, bucket);
-  if (opts && opts->engine != TQ_ENGINE_AUTO && opts->engine != sh.engine) {
-    sh.engine = opts->engine;
-    if (sh.engine == TQ_ENGINE_MATRIX) sh.qtile = bucket > 64 ? 128 : 64;
-    else sh.qtile = default_shape(db, k, bucket).qtile;
+  int engine = opts ? opts->engine : TQ_ENGINE_AUTO;
+  const int qtile = opts ? opts->qtile : 0;
+  if (engine == TQ_ENGINE_AUTO && qtile > 0) engine = qtile >= 64 ? TQ_ENGINE_MATRIX : TQ_ENGINE_POPCOUNT;
+  if (engine != TQ_ENGINE_AUTO && engine != sh.engine) {
+    sh.engine = engine;
+    if (engine == TQ_ENGINE_MATRIX) {
+      sh.qtile = 64;
+    } else {
+      const int qmax = tqi::batched_max_qtile(k);
+      sh.qtile = std::min(qmax, bucket <= 2 ? 2 : bucket <= 4 ? 4 : bucket <= 8 ? 8 : 16);
+    }
   }
-  if (opts && opts->qtile > 0) sh.qtile = opts->qtile;
+  if (qtile > 0) sh.qtile = qtile;
   if (opts && opts->grid > 0) sh.grid = opts->grid;
   return sh;
 }
@@ -277,15 +306,15 @@ int search_batched(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *id
                    const tq_search_opts *opts, hipStream_t s) {
   const bool use_graph = opts ? opts->use_graph != 0 : true;
   const int engine = opts ? opts->engine : TQ_ENGINE_AUTO;
+  const int q = opts ? opts->qtile : 0;
   if (engine < TQ_ENGINE_AUTO || engine > TQ_ENGINE_MATRIX) return fail(TQ_ERR_INVALID, "unknown engine %d", engine);
-  if (engine == TQ_ENGINE_MATRIX && tqi::rows_for_k(k) > 2)
-    return fail(TQ_ERR_INVALID, "the matrix engine supports k <= 128 (k=%d)", k);
-  if (opts && opts->qtile > 0) {
-    const int q = opts->qtile;
-    if (engine == TQ_ENGINE_MATRIX) {
+  const bool matrix = engine == TQ_ENGINE_MATRIX || (engine == TQ_ENGINE_AUTO && q >= 64);
+  if (matrix && tqi::rows_for_k(k) > 2) return fail(TQ_ERR_INVALID, "the matrix engine supports k <= 128 (k=%d)", k);
+  if (q > 0) {
+    if (matrix) {
       if (q != 64 && q != 128) return fail(TQ_ERR_INVALID, "matrix engine: qtile=%d is not 64 or 128", q);
     } else {
-      if (q != 2 && q != 4 && q != 8 && q != 16) return fail(TQ_ERR_INVALID, "qtile=%d is not 2, 4, 8 or 16", q);
+      if (q != 2 && q != 4 && q != 8 && q != 16) return fail(TQ_ERR_INVALID, "qtile=%d is not 2, 4, 8, 16, 64 or 128", q);
       if (q > tqi::batched_max_qtile(k))
         return fail(TQ_ERR_INVALID, "qtile=%d exceeds %d for k=%d", q, tqi::batched_max_qtile(k), k);
     }

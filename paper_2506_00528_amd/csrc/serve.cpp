@@ -197,7 +197,9 @@ hipError_t enqueue_tick(tq_server *s, TickPlan &p, TickStage &st) {
   const int nq = static_cast<int>(p.slots.size());
   const int nret = static_cast<int>(p.retire.size());
   const int kt = p.k;  // the tick's k: the largest k of the active requests
-  const int qtile = std::min(s->qtile, tqi::batched_max_qtile(kt));
+  const int nq_all = static_cast<int>(p.slots.size());
+  const bool matrix = default_engine(kt, nq_all) == TQ_ENGINE_MATRIX;
+  const int qtile = matrix ? 64 : std::min(s->qtile, tqi::batched_max_qtile(kt));
   tqi::BatchParams b;
   const int64_t lo = p.seg * s->seg_tiles;
   const int64_t hi = std::min<int64_t>(db.ntiles, lo + s->seg_tiles);
@@ -222,7 +224,8 @@ hipError_t enqueue_tick(tq_server *s, TickPlan &p, TickStage &st) {
   if (e != hipSuccess) return e;
   {
     TimedLaunch t(kTimeBatched, s->stream);
-    e = tqi::scan_batched_launch(db, s->d_qtick, s->d_prm, kt, qtile, s->grid, s->d_partial, s->stream);
+    e = matrix ? tqi::scan_mfma_launch(db, s->d_qtick, s->d_prm, kt, qtile, s->grid, s->d_partial, s->stream)
+               : tqi::scan_batched_launch(db, s->d_qtick, s->d_prm, kt, qtile, s->grid, s->d_partial, s->stream);
   }
   if (e != hipSuccess) return e;
   e = tqi::merge_batched_launch(s->d_partial, s->d_prm, nq, kt, s->grid + tqi::kXcds, s->d_mid, s->stream);
@@ -446,8 +449,9 @@ int tq_serve_create(const tq_db *db, const tq_serve_cfg *cfg, tq_server **out) {
   dm((void **)&s->d_qrows, M * 8 * nc * sizeof(uint32_t));
   dm((void **)&s->d_qtick, M * 8 * nc * sizeof(uint32_t));
   dm((void **)&s->d_running, M * s->k_run * sizeof(uint64_t));
+  // query tiles of up to 64 (matrix engine) or s->qtile (popcount engine)
   dm((void **)&s->d_partial,
-     (static_cast<size_t>(s->qtile) * s->grid + (tqi::kXcds + 1) * M) * s->k_run * sizeof(uint64_t));
+     (static_cast<size_t>(std::max(64, s->qtile)) * s->grid + (tqi::kXcds + 1) * M) * s->k_run * sizeof(uint64_t));
   int64_t mid_keys = 0;
   for (int k = 1; k <= s->k_run; ++k)
     mid_keys = std::max(mid_keys, tqi::merge_batched_mid_keys(static_cast<int>(M), s->grid + tqi::kXcds, k));

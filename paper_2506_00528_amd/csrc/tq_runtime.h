@@ -101,5 +101,6 @@ int search_batched(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *id
                    const tq_search_opts *opts, hipStream_t s);
 void batched_release(tq_db *db);
 int autotune(tq_db *db, int nq_max, const int *ks, int nks, hipStream_t s, int verbose);
+int default_engine(int k, int nq);
 
 }  // namespace tqr
