@@ -44,6 +44,8 @@ def parse():
     p.add_argument("--x", type=int, default=0, help="EVP x (default: the workload's)")
     p.add_argument("--batch", type=int, default=100, help="queries per step")
     p.add_argument("--path", default="plain", choices=["plain", "batched", "auto"])
+    p.add_argument("--engine", default="matrix", choices=["matrix", "popcount"],
+                   help="batched path: engine timed by --path batched")
     p.add_argument("--grid", type=int, default=0)
     p.add_argument("--recall-queries", type=int, default=100)
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -96,18 +98,34 @@ def run_batching(tq, torch, db, queries, x, n, W, plain_qps, args, log):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
     total_q = sum(b for b, _ in batches)
-    # roofline of the batched scan kernel on the first 50 batches (direct launches, timed)
-    tq.tq_timing_read(1, reset=True)
-    tq.tq_timing_enable(True)
-    for i in range(min(50, len(batches))):
-        one(i)
-    torch.cuda.synchronize()
-    tq.tq_timing_enable(False)
-    kms, launches = tq.tq_timing_read(1, reset=True)
-    pairs = sum(b for b, _ in batches[:min(50, len(batches))]) * n
+    # rooflines on the first 50 batches (direct launches, HIP events around each scan):
+    # the matrix engine (what the tuned path runs for these k) against the fp4 MFMA
+    # peak, and the popcount engine against the integer VALU peak
+    nb = min(50, len(batches))
+    pairs = sum(b for b, _ in batches[:nb]) * n
+    d_pad = 128 * ((W * 32 + 127) // 128)  # K of the fp4 products (d padded to 128)
+
+    def timed(engine):
+        tq.tq_timing_read(1, reset=True)
+        tq.tq_timing_enable(True)
+        for i in range(nb):
+            b, k = batches[i]
+            q0 = int(offs[i])
+            tq.tq_encode(queries[q0:q0 + b], x, qc[:b])
+            ids, sc = outs[k]
+            tq.tq_search_knn(db, qc[:b], k, path=tq.TQ_PATH_BATCHED, engine=engine, ids=ids[:b], scores=sc[:b])
+        torch.cuda.synchronize()
+        tq.tq_timing_enable(False)
+        return tq.tq_timing_read(1, reset=True)
+
+    kms_m, launches_m = timed(tq.TQ_ENGINE_MATRIX)
+    kms_p, launches_p = timed(tq.TQ_ENGINE_POPCOUNT)
+    flops = 2.0 * pairs * d_pad
+    tflops = flops / (kms_m * 1e-3) / 1e12
+    fp4_peak = 10100.0  # dense fp4 MFMA, TFLOP/s
     ops_per_pair = 5 * 4 * ((W + 3) // 4)
-    peak = 256 * 64 * 2.4e9 / 1e12
-    tops = pairs * ops_per_pair / (kms * 1e-3) / 1e12
+    valu_peak = 256 * 64 * 2.4e9 / 1e12
+    tops = pairs * ops_per_pair / (kms_p * 1e-3) / 1e12
     # consistency: a few batches against the plain path
     ok = True
     for i in (0, 7, 123):
@@ -123,10 +141,14 @@ def run_batching(tq, torch, db, queries, x, n, W, plain_qps, args, log):
             "queries": total_q, "seconds": round(dt, 3), "qps": round(total_q / dt, 1),
             "vs_plain": round(total_q / dt / plain_qps, 2), "autotune_s": round(tune_s, 1),
             "same_results_as_plain": ok,
-            "roofline": {"kernel": "scan_batched_kernel", "bound": "alu", "achieved": round(tops, 2),
-                         "peak": round(peak, 2), "unit": "Tops/s", "frac": round(tops / peak, 4),
-                         "ops_per_pair": ops_per_pair, "launches": launches,
-                         "avg_launch_ms": round(kms / max(1, launches), 4)}}
+            "roofline": {"kernel": "scan_mfma_kernel", "bound": "mfma", "achieved": round(tflops, 1),
+                         "peak": fp4_peak, "unit": "TFLOP/s", "frac": round(tflops / fp4_peak, 4),
+                         "flops_per_pair": 2 * d_pad, "batches": nb, "launches": launches_m,
+                         "avg_launch_ms": round(kms_m / max(1, launches_m), 4)},
+            "roofline_popcount": {"kernel": "scan_batched_kernel", "bound": "alu", "achieved": round(tops, 2),
+                                  "peak": round(valu_peak, 2), "unit": "Tops/s", "frac": round(tops / valu_peak, 4),
+                                  "ops_per_pair": ops_per_pair, "batches": nb, "launches": launches_p,
+                                  "avg_launch_ms": round(kms_p / max(1, launches_p), 4)}}
 
 
 def run_serving(tq, torch, args, log):
@@ -312,8 +334,10 @@ def main():
     def step(i):
         q0 = (i * B) % max(1, nq_total - B + 1)
         tq.tq_encode(queries[q0:q0 + B], x, qc)
-        tq.tq_search_knn(db, qc, k, path=path, grid=args.grid, ids=out_ids, scores=out_sc)
+        tq.tq_search_knn(db, qc, k, path=path, grid=args.grid, ids=out_ids, scores=out_sc, engine=engine)
 
+    engine = {"matrix": tq.TQ_ENGINE_MATRIX, "popcount": tq.TQ_ENGINE_POPCOUNT}[args.engine] \
+        if args.path == "batched" else tq.TQ_ENGINE_AUTO
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
@@ -379,7 +403,7 @@ def main():
                      "traffic": traffic, "bytes_per_launch": db_bytes,
                      "avg_launch_ms": round(avg_launch_ms, 5), "launches": launches},
     }
-    if args.path == "batched":
+    if args.path == "batched" and args.engine == "popcount":
         ops = B * n * ops_per_pair
         tops = ops / (avg_launch_ms * 1e-3) / 1e12
         result["hbm_gbps"] = None
@@ -387,6 +411,15 @@ def main():
         result["roofline"] = {"kernel": "scan_batched_kernel", "bound": "alu", "achieved": round(tops, 2),
                               "peak": round(valu_peak_tops, 2), "unit": "Tops/s", "frac": round(tops / valu_peak_tops, 4),
                               "traffic": None, "ops_per_launch": ops, "ops_per_pair": ops_per_pair,
+                              "avg_launch_ms": round(avg_launch_ms, 5), "launches": launches}
+    elif args.path == "batched":
+        d_pad = 128 * ((W * 32 + 127) // 128)
+        tflops = 2.0 * B * n * d_pad / (avg_launch_ms * 1e-3) / 1e12
+        result["hbm_gbps"] = None
+        result["hbm_frac"] = None
+        result["roofline"] = {"kernel": "scan_mfma_kernel", "bound": "mfma", "achieved": round(tflops, 1),
+                              "peak": 10100.0, "unit": "TFLOP/s", "frac": round(tflops / 10100.0, 4),
+                              "traffic": None, "flops_per_pair": 2 * d_pad,
                               "avg_launch_ms": round(avg_launch_ms, 5), "launches": launches}
 
     if args.copy_probe:
