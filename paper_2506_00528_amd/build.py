@@ -21,8 +21,12 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libtq.so")
 ARCH = os.environ.get("TQ_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["encode.hip", "layout.hip", "scan.hip", "batched_kernels.hip", "mfma_kernels.hip", "api.cpp", "search.cpp",
-           "batched.cpp", "serve.cpp"]
+# (source, plane width): the matrix-core kernels are compiled once per plane
+# width (16-byte chunks per plane, 1..8) so their instantiations build in
+# parallel; every other source is compiled once.  Slowest first.
+SOURCES = [("mfma_kernels.hip", nc) for nc in range(8, 0, -1)] + \
+          [("scan.hip", 0), ("batched_kernels.hip", 0), ("encode.hip", 0), ("layout.hip", 0),
+           ("api.cpp", 0), ("search.cpp", 0), ("batched.cpp", 0), ("serve.cpp", 0)]
 
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result",
@@ -39,10 +43,12 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+def _compile(item: tuple, verbose: bool) -> str:
+    src, nc = item
+    obj = os.path.join(BUILD, os.path.basename(src) + (f".nc{nc}" if nc else "") + ".o")
     lang = [] if src.endswith(".hip") else ["-x", "hip"]
-    cmd = [hipcc()] + lang + CFLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    defs = [f"-DTQ_NC={nc}"] if nc else []
+    cmd = [hipcc()] + lang + CFLAGS + defs + ["-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -57,7 +63,7 @@ def _compile(src: str, verbose: bool) -> str:
 
 def build(verbose: bool = False, jobs: int | None = None) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s[0]))]
     jobs = jobs or min(len(srcs), max(1, min(16, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), srcs))

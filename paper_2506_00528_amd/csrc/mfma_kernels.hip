@@ -65,28 +65,43 @@ __device__ __forceinline__ float score_of(uint64_t thr) {
   return thr ? static_cast<float>(key_score(thr)) : -1e30f;
 }
 
-// Staging of one 64-vector tile: thread j re-codes the words that lane j % 64
-// of every wave reads for column block (j / 64) at each K-step, i.e. word
-// 4s + (j % 64) / 16 of vector 16 (j / 64) + j % 16, for s = 0 .. NC-1.
+// Staging of one 64-vector tile.  Thread j reads 16-byte chunks s = j / 64,
+// j / 64 + 4 (< NC) of both planes of vector v = j % 64 -- a wave reads one
+// contiguous 1 KiB run per load -- and re-codes word w of chunk s into the
+// operand that lane 16 w + v % 16 of every wave takes for column block v / 16
+// at K-step s.  The loads are ordinary (cached) loads: the workgroups that
+// scan the same database part for other query tiles run at the same time on
+// the same XCD and find the tile in its L2.
 template <int NC>
 struct TileStage {
-  uint32_t nz[NC], ng[NC];
+  static constexpr int kPer = (NC + 3) / 4;
+  uint4 nz[kPer], ng[kPer];
 
-  __device__ __forceinline__ void load(const uint32_t *__restrict__ words, int64_t t, int j) {
-    const int lane = j & 63, cb = j >> 6;
-    const int v = cb * 16 + (lane & 15), grp = lane >> 4;
+  __device__ __forceinline__ void load(const uint4 *__restrict__ tiles, int64_t t, int j) {
+    const int v = j & 63, s0 = j >> 6;
 #pragma unroll
-    for (int s = 0; s < NC; ++s) {
-      const int64_t i0 = ((t * 2 + 0) * NC + s) * 64 + v;
-      const int64_t i1 = ((t * 2 + 1) * NC + s) * 64 + v;
-      nz[s] = __builtin_nontemporal_load(words + i0 * 4 + grp);
-      ng[s] = __builtin_nontemporal_load(words + i1 * 4 + grp);
+    for (int i = 0; i < kPer; ++i) {
+      const int s = s0 + 4 * i;
+      if (s < NC) {
+        nz[i] = tiles[((t * 2 + 0) * NC + s) * 64 + v];
+        ng[i] = tiles[((t * 2 + 1) * NC + s) * 64 + v];
+      }
     }
   }
   // operand (s, cb) of lane l lives at op[(s * 4 + cb) * 64 + l]
   __device__ __forceinline__ void store(v4i *op, int j) const {
+    const int v = j & 63, s0 = j >> 6;
+    v4i *dst = op + (v >> 4) * 64 + (v & 15);
 #pragma unroll
-    for (int s = 0; s < NC; ++s) op[s * 256 + j] = fp4_operand(nz[s], ng[s]);
+    for (int i = 0; i < kPer; ++i) {
+      const int s = s0 + 4 * i;
+      if (s < NC) {
+        dst[s * 256 + 0] = fp4_operand(nz[i].x, ng[i].x);
+        dst[s * 256 + 16] = fp4_operand(nz[i].y, ng[i].y);
+        dst[s * 256 + 32] = fp4_operand(nz[i].z, ng[i].z);
+        dst[s * 256 + 48] = fp4_operand(nz[i].w, ng[i].w);
+      }
+    }
   }
 };
 
@@ -108,7 +123,6 @@ __global__ __launch_bounds__(kMfmaBlock) void scan_mfma_kernel(const uint4 *__re
   const int64_t tile_lo = prm->tile_lo, tile_hi = prm->tile_hi;
   const int items = nqt * parts;
   const int km1 = k - 1;
-  const uint32_t *words = reinterpret_cast<const uint32_t *>(tiles);
 
   for (int item = blockIdx.x; item < items; item += gridDim.x) {
     int qt, part;
@@ -145,17 +159,13 @@ __global__ __launch_bounds__(kMfmaBlock) void scan_mfma_kernel(const uint4 *__re
 #pragma unroll
       for (int i = 0; i < 4; ++i) tv[rb][i] = (rb * 16 + 4 * grp + i < nact) ? -1e30f : 1e30f;
 
-    TileStage<NC> stage;
-    if (t0 < t1) {
-      stage.load(words, t0, j);
-      stage.store(op[0], j);
-    }
-    __syncthreads();
-    for (int64_t t = t0; t < t1; ++t) {
-      const int buf = static_cast<int>((t - t0) & 1);
-      const bool more = t + 1 < t1;
-      if (more) stage.load(words, t + 1, j);  // in flight during the products
-
+    // Pipeline: while tile t is multiplied out of LDS, tile t + 1 (loaded
+    // during the previous tile) is re-coded into the other LDS buffer and
+    // tile t + 2 is in flight to registers.  Loads past the part re-read its
+    // last tile, so every thread issues the same loads on every step.
+    TileStage<NC> sa, sb;
+    auto step = [&](int64_t t, const v4i *cur, v4i *nxt, TileStage<NC> &fill, const TileStage<NC> &ready) {
+      fill.load(tiles, min(t + 2, t1 - 1), j);
       if (nact > 0) {
         v4f acc[RB][4];
 #pragma unroll
@@ -166,7 +176,7 @@ __global__ __launch_bounds__(kMfmaBlock) void scan_mfma_kernel(const uint4 *__re
         for (int s = 0; s < NC; ++s) {
 #pragma unroll
           for (int cb = 0; cb < 4; ++cb) {
-            const v4i b = op[buf][(s * 4 + cb) * 64 + lane];
+            const v4i b = cur[(s * 4 + cb) * 64 + lane];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) acc[rb][cb] = mfma_fp4(a[rb][s], b, acc[rb][cb]);
           }
@@ -218,8 +228,18 @@ __global__ __launch_bounds__(kMfmaBlock) void scan_mfma_kernel(const uint4 *__re
           }
         }
       }
-      if (more) stage.store(op[buf ^ 1], j);
+      ready.store(nxt, j);
       __syncthreads();
+    };
+    if (t0 < t1) {
+      sa.load(tiles, t0, j);
+      sb.load(tiles, min(t0 + 1, t1 - 1), j);
+      sa.store(op[0], j);
+      __syncthreads();
+      for (int64_t t = t0; t < t1; t += 2) {
+        step(t, op[0], op[1], sa, sb);
+        if (t + 1 < t1) step(t + 1, op[1], op[0], sb, sa);
+      }
     }
 
     // a query belongs to one wave: its list is the (query, part) result
@@ -245,9 +265,11 @@ hipError_t launch_m3(const DbDev &db, const uint32_t *qprep, const BatchParams *
   return hipGetLastError();
 }
 
+}  // namespace
+
 template <int NC>
-hipError_t launch_m1(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile, int grid,
-                     uint64_t *partial, hipStream_t s) {
+hipError_t scan_mfma_launch_nc(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile,
+                               int grid, uint64_t *partial, hipStream_t s) {
   const int r = rows_for_k(k);
   if (qtile == 64) return r == 1 ? launch_m3<NC, 1, 1>(db, qprep, prm, k, grid, partial, s)
                                  : launch_m3<NC, 2, 1>(db, qprep, prm, k, grid, partial, s);
@@ -255,24 +277,12 @@ hipError_t launch_m1(const DbDev &db, const uint32_t *qprep, const BatchParams *
                 : launch_m3<NC, 2, 2>(db, qprep, prm, k, grid, partial, s);
 }
 
-}  // namespace
-
-bool mfma_supported(int k, int qtile) { return rows_for_k(k) <= 2 && (qtile == 64 || qtile == 128); }
-
-hipError_t scan_mfma_launch(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile,
-                            int grid, uint64_t *partial, hipStream_t s) {
-  if (!mfma_supported(k, qtile)) return hipErrorInvalidValue;
-  switch (db.nc) {
-    case 1: return launch_m1<1>(db, qprep, prm, k, qtile, grid, partial, s);
-    case 2: return launch_m1<2>(db, qprep, prm, k, qtile, grid, partial, s);
-    case 3: return launch_m1<3>(db, qprep, prm, k, qtile, grid, partial, s);
-    case 4: return launch_m1<4>(db, qprep, prm, k, qtile, grid, partial, s);
-    case 5: return launch_m1<5>(db, qprep, prm, k, qtile, grid, partial, s);
-    case 6: return launch_m1<6>(db, qprep, prm, k, qtile, grid, partial, s);
-    case 7: return launch_m1<7>(db, qprep, prm, k, qtile, grid, partial, s);
-    case 8: return launch_m1<8>(db, qprep, prm, k, qtile, grid, partial, s);
-    default: return hipErrorInvalidValue;
-  }
-}
+// This file is compiled once per plane width (-DTQ_NC=1..8), so that the
+// eight instantiations build in parallel.
+#ifndef TQ_NC
+#error "compile mfma_kernels.hip with -DTQ_NC=<1..8>"
+#endif
+template hipError_t scan_mfma_launch_nc<TQ_NC>(const DbDev &, const uint32_t *, const BatchParams *, int, int, int,
+                                               uint64_t *, hipStream_t);
 
 }  // namespace tqi

@@ -72,6 +72,10 @@ hipError_t scan_batched_launch(const DbDev &db, const uint32_t *qprep, const Bat
 bool mfma_supported(int k, int qtile);
 hipError_t scan_mfma_launch(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile,
                             int grid, uint64_t *partial, hipStream_t s);
+// one plane width (mfma_kernels.hip, compiled per NC); called by scan_mfma_launch
+template <int NC>
+hipError_t scan_mfma_launch_nc(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile,
+                               int grid, uint64_t *partial, hipStream_t s);
 // Per-query merge of the (query, part) lists; the query count, part count and
 // output pointers come from `prm`; at most max_parts parts per query.  With
 // prm->running set, each query's running list joins the merge and receives
