@@ -5,122 +5,233 @@
 // is read with coalesced loads and every 64-bit ballot over one register is
 // exactly two 32-bit words of a bit plane (coordinates 64j .. 64j+63).
 //
-// Selecting the x largest magnitudes: |u_i| is compared as the unsigned bit
-// pattern of the float with its sign cleared, which orders finite floats
-// exactly (subnormals included).  A bisection over those 31-bit patterns
-// finds the x-th largest magnitude t (the largest t with count(|u| >= t) >=
-// x); it stops early at any cut with exactly x magnitudes at or above it.
+// Selecting the x largest magnitudes: magnitudes are compared as floats
+// with the sign dropped (|u_i|), which orders finite values exactly like the
+// unsigned bit patterns of |u_i| (subnormals included: f32 denormals are not
+// flushed).  The x-th largest magnitude t is the largest pattern with
+// count(|u| >= t) >= x; it is found by a binary search over patterns on an
+// interval [lo, hi) with count(>= lo) >= x > count(>= hi), stopping early at
+// any cut with exactly x magnitudes at or above it.
+//   * A wave scans rows one after another, and rows of one data set have
+//     similar thresholds, so the search starts by bracketing the previous
+//     row's t with galloping steps (a good guess only saves work; the result
+//     never depends on it).
+//   * Each count over the whole row costs one compare and one ballot per
+//     register.  Once the interval holds at most 64 magnitudes, they are
+//     compacted through LDS into one value per lane and the rest of the
+//     search costs one compare per step.
 // Then every coordinate above t is taken, and among those equal to t the
-// lowest indices fill the remaining places (ties go to the lower index).
-// The sign is "-1 iff u_i < 0", i.e. sign bit set and magnitude non-zero, so
-// both zeros give +1.
+// lowest indices fill the remaining places (ties go to the lower index).  The
+// sign is "-1 iff u_i < 0" (a float compare), so both zeros give +1.
+#include <utility>
+
 #include "tq_internal.h"
 
 namespace tqi {
 namespace {
 
 constexpr int kEncodeBlock = 256;
+// First bracketing step, in magnitude patterns: 1/16 of a binade (measured
+// best among 2^13 .. 2^22 on the Gaussian-mixture workloads at d = 384 .. 1024).
+constexpr uint32_t kGallop = 1u << 19;
+constexpr uint32_t kInfBits = 0x7F800000u;  // above every finite magnitude
 
-template <int J>
+__device__ __forceinline__ int popc64(uint64_t m) { return __popcll(m); }
+
+// lanes whose predicate holds (the compare masks combine without a detour
+// through a 0/1 integer)
+__device__ __forceinline__ uint64_t vote(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+__device__ __forceinline__ float pat(uint32_t p) { return __uint_as_float(p); }
+
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+  return static_cast<int>(
+      __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32), __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u)));
+}
+
+// v with lane L replaced by the uniform value `val` (v_writelane_b32)
+template <int L>
+__device__ __forceinline__ uint32_t put_lane(uint32_t v, uint32_t val) {
+  asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(val), "n"(L));
+  return v;
+}
+
+// Plane words 2j and 2j+1 (coordinates 64j .. 64j+63) of the selection
+// sel(j): the v+ words go to lanes 2j, 2j+1 of *plus, the v- words to the same
+// lanes of *minus.
+template <int J, typename Sel, int... Js>
+__device__ __forceinline__ void pack_planes(const float (&v)[J], Sel sel, uint32_t *plus, uint32_t *minus,
+                                            std::integer_sequence<int, Js...>) {
+  auto one = [&](auto jc) {
+    constexpr int j = decltype(jc)::value;
+    const uint64_t s = sel(j);
+    const uint64_t neg = vote(v[j] < 0.0f);
+    const uint64_t p = s & ~neg, m = s & neg;
+    *plus = put_lane<2 * j>(*plus, static_cast<uint32_t>(p));
+    *plus = put_lane<2 * j + 1>(*plus, static_cast<uint32_t>(p >> 32));
+    *minus = put_lane<2 * j>(*minus, static_cast<uint32_t>(m));
+    *minus = put_lane<2 * j + 1>(*minus, static_cast<uint32_t>(m >> 32));
+  };
+  (one(std::integral_constant<int, Js>{}), ...);
+}
+
+// J registers of 64 coordinates per row; the first JV are always inside the
+// row (d > 64 JV for every d this instantiation serves).
+template <int J, int JV>
 __global__ __launch_bounds__(kEncodeBlock) void encode_kernel(const float *__restrict__ X, int64_t n,
                                                              int d, int x, int W,
                                                              uint32_t *__restrict__ codes,
                                                              int *__restrict__ flags) {
-  constexpr int kWordsPerLane = (4 * J + 63) / 64;  // 2W <= 4J code words per row
+  // 2W <= 4J <= 64 code words per row: one word per lane
+  __shared__ uint32_t pool[kEncodeBlock];
   const int lane = threadIdx.x & 63;
+  uint32_t *slot = pool + (threadIdx.x & ~63);  // this wave's 64 compaction slots
   const int64_t waves_per_block = kEncodeBlock / 64;
   const int64_t nwaves = static_cast<int64_t>(gridDim.x) * waves_per_block;
   const int row_words = 2 * W;
+  uint32_t guess = 0;  // threshold of this wave's previous row (0: none yet)
 
   for (int64_t row = static_cast<int64_t>(blockIdx.x) * waves_per_block + (threadIdx.x >> 6); row < n;
        row += nwaves) {
-    const float *u = X + row * d;
-    uint32_t mag[J];
-    bool neg[J], valid[J];
-    bool bad = false;
+    const float *u = X + row * d + lane;
+    float v[J];
+    uint32_t top = 0;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-      const int i = j * 64 + lane;
-      valid[j] = i < d;
-      uint32_t bits = 0;
-      if (valid[j]) bits = __float_as_uint(__builtin_nontemporal_load(u + i));
-      mag[j] = bits & 0x7FFFFFFFu;
-      neg[j] = (bits >> 31) != 0 && mag[j] != 0;
-      bad |= mag[j] >= 0x7F800000u;  // infinity or NaN
+      if (j < JV) v[j] = __builtin_nontemporal_load(u + 64 * j);
+      else v[j] = j * 64 + lane < d ? __builtin_nontemporal_load(u + 64 * j) : 0.0f;
+      top = max(top, __float_as_uint(v[j]) & 0x7FFFFFFFu);
     }
-    uint32_t out[kWordsPerLane];
-#pragma unroll
-    for (int s = 0; s < kWordsPerLane; ++s) out[s] = 0;
+    auto valid = [&](int j) { return j < JV || j * 64 + lane < d; };
+    uint32_t plus = 0, minus = 0;
 
-    if (__any(bad)) {
+    if (__any(top >= kInfBits)) {  // infinity or NaN
       if (lane == 0) atomicOr(flags, 1);
     } else {
-      // --- the x-th largest magnitude -------------------------------------
-      uint32_t t = 0;       // invariant: count(mag >= t) >= x
-      uint32_t cut = 0;     // set when a cut with exactly x at or above is met
-      for (int b = 30; b >= 0; --b) {
-        const uint32_t cand = t | (1u << b);
+      // count(|u| >= c) over the row, for patterns c >= 1 (padding holds 0)
+      auto count_ge = [&](uint32_t c) {
+        const float cf = pat(c);
         int cnt = 0;
 #pragma unroll
-        for (int j = 0; j < J; ++j) cnt += __popcll(__ballot(mag[j] >= cand));
-        if (cnt == x) {
-          cut = cand;
-          break;
+        for (int j = 0; j < J; ++j) cnt += popc64(vote(fabsf(v[j]) >= cf));
+        return cnt;
+      };
+      uint32_t lo = 0, hi = kInfBits, cut = 0;
+      int clo = d, chi = 0;  // count(|u| >= lo), count(|u| >= hi)
+      // --- bracket the previous row's threshold ---------------------------
+      if (guess != 0) {
+        const int c = count_ge(guess);
+        if (c == x) {
+          cut = guess;
+        } else if (c > x) {
+          lo = guess;
+          clo = c;
+          for (uint32_t step = kGallop; step < hi - lo; step <<= 1) {
+            const uint32_t h = lo + step;
+            const int ch = count_ge(h);
+            if (ch == x) {
+              cut = h;
+              break;
+            }
+            if (ch < x) {
+              hi = h;
+              chi = ch;
+              break;
+            }
+            lo = h;
+            clo = ch;
+          }
+        } else {
+          hi = guess;
+          chi = c;
+          for (uint32_t step = kGallop; step < hi - lo; step <<= 1) {
+            const uint32_t l = hi - step;
+            const int cl = count_ge(l);
+            if (cl == x) {
+              cut = l;
+              break;
+            }
+            if (cl > x) {
+              lo = l;
+              clo = cl;
+              break;
+            }
+            hi = l;
+            chi = cl;
+          }
         }
-        if (cnt > x) t = cand;
       }
-      // take mag >= lo outright; if there was no exact cut, also take the
-      // lowest-index `need` coordinates with mag == t
-      const bool exact = cut != 0;
-      const uint32_t lo = exact ? cut : t + 1;
-      int above = 0;
+      // --- halve on the whole row while the interval holds > 64 ------------
+      while (cut == 0 && clo - chi > 64 && hi - lo > 1) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        const int c = count_ge(mid);
+        if (c == x) cut = mid;
+        else if (c > x) lo = mid, clo = c;
+        else hi = mid, chi = c;
+      }
+      // --- compact the interval's magnitudes into one register, finish ----
+      if (cut == 0 && hi - lo > 1) {
+        const float lof = pat(lo), hif = pat(hi);
+        int base = 0;
 #pragma unroll
-      for (int j = 0; j < J; ++j) above += __popcll(__ballot(mag[j] >= lo));
-      const int need = x - above;
-      int eq_before = 0;
-#pragma unroll
-      for (int j = 0; j < J; ++j) {
-        const uint64_t gt = __ballot(mag[j] >= lo);
-        const uint64_t eq = exact ? 0ull : __ballot(valid[j] && mag[j] == t);
-        const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
-            static_cast<uint32_t>(eq >> 32), __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(eq), 0u));
-        const bool take = ((eq >> lane) & 1ull) && (eq_before + static_cast<int>(rank) < need);
-        const uint64_t sel = gt | __ballot(take);
-        eq_before += __popcll(eq);
-        const uint64_t negm = __ballot(neg[j]);
-        const uint64_t plus = sel & ~negm;
-        const uint64_t minus = sel & negm;
-        // plane words 2j and 2j+1 (coordinates 64j .. 64j+63)
-        const uint32_t wv[4] = {static_cast<uint32_t>(plus), static_cast<uint32_t>(plus >> 32),
-                                static_cast<uint32_t>(minus), static_cast<uint32_t>(minus >> 32)};
-#pragma unroll
-        for (int h = 0; h < 4; ++h) {
-          const int pw = 2 * j + (h & 1);  // word within the plane
-          if (pw >= W) continue;
-          const int w = (h < 2 ? 0 : W) + pw;  // word within the row
-#pragma unroll
-          for (int s = 0; s < kWordsPerLane; ++s)
-            if (w == s * 64 + lane) out[s] = wv[h];
+        for (int j = 0; j < J; ++j) {
+          const bool in = valid(j) && fabsf(v[j]) >= lof && fabsf(v[j]) < hif;
+          const uint64_t m = vote(in);
+          if (in) slot[base + lanes_below(m)] = __float_as_uint(v[j]);
+          base += popc64(m);
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const float m2 = lane < base ? fabsf(__uint_as_float(slot[lane])) : 0.0f;
+        const int chi0 = chi;  // every magnitude >= hi is outside the register
+        while (hi - lo > 1) {
+          const uint32_t mid = lo + ((hi - lo) >> 1);
+          const int c = chi0 + popc64(vote(m2 >= pat(mid)));
+          if (c == x) {
+            cut = mid;
+            break;
+          }
+          if (c > x) lo = mid, clo = c;
+          else hi = mid, chi = c;
+        }
+        __builtin_amdgcn_wave_barrier();  // the slots are rewritten by the next row
+      }
+      constexpr auto js = std::make_integer_sequence<int, J>{};
+      if (cut != 0) {
+        // exactly x magnitudes are >= cut
+        guess = cut;
+        const float cf = pat(cut);
+        pack_planes<J>(v, [&](int j) { return vote(fabsf(v[j]) >= cf); }, &plus, &minus, js);
+      } else {
+        // t = lo and chi = count(|u| > t): the lowest-index x - chi
+        // coordinates with |u| == t complete the set
+        guess = lo;
+        const float tf = pat(lo);
+        const int need = x - chi;
+        int eq_before = 0;
+        pack_planes<J>(v, [&](int j) {
+          const uint64_t eq = vote(valid(j) && fabsf(v[j]) == tf);
+          const bool take = ((eq >> lane) & 1ull) && eq_before + lanes_below(eq) < need;
+          eq_before += popc64(eq);
+          return vote(fabsf(v[j]) > tf) | vote(take);
+        }, &plus, &minus, js);
       }
     }
-    uint32_t *dst = codes + row * row_words;
-#pragma unroll
-    for (int s = 0; s < kWordsPerLane; ++s) {
-      const int w = s * 64 + lane;
-      if (w < row_words) dst[w] = out[s];
-    }
+    // lane w < W holds v+ word w; lane w >= W takes v- word w - W
+    const uint32_t mw = __shfl(minus, lane - W);
+    if (lane < row_words) codes[row * row_words + lane] = lane < W ? plus : mw;
   }
 }
 
-template <int J>
+template <int J, int JV>
 hipError_t launch_j(const float *X, int64_t n, int d, int x, uint32_t *codes, int *flags, int num_cu,
                     hipStream_t s) {
   int64_t blocks = (n + 3) / 4;  // one wave per row, four waves per block
-  const int64_t cap = static_cast<int64_t>(num_cu > 0 ? num_cu : 256) * 16;
+  const int64_t cap = static_cast<int64_t>(num_cu > 0 ? num_cu : 256) * 8;
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(encode_kernel<J>, dim3(static_cast<unsigned>(blocks)), dim3(kEncodeBlock), 0, s, X,
+  hipLaunchKernelGGL((encode_kernel<J, JV>), dim3(static_cast<unsigned>(blocks)), dim3(kEncodeBlock), 0, s, X,
                      n, d, x, (d + 31) / 32, codes, flags);
   return hipGetLastError();
 }
@@ -131,13 +242,13 @@ hipError_t encode_launch(const float *X, int64_t n, int d, int x, uint32_t *code
                          int num_cu, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const int j = (d + 63) / 64;
-  if (j <= 1) return launch_j<1>(X, n, d, x, codes, flags, num_cu, s);
-  if (j <= 2) return launch_j<2>(X, n, d, x, codes, flags, num_cu, s);
-  if (j <= 4) return launch_j<4>(X, n, d, x, codes, flags, num_cu, s);
-  if (j <= 6) return launch_j<6>(X, n, d, x, codes, flags, num_cu, s);
-  if (j <= 8) return launch_j<8>(X, n, d, x, codes, flags, num_cu, s);
-  if (j <= 12) return launch_j<12>(X, n, d, x, codes, flags, num_cu, s);
-  return launch_j<16>(X, n, d, x, codes, flags, num_cu, s);
+  if (j <= 1) return launch_j<1, 0>(X, n, d, x, codes, flags, num_cu, s);
+  if (j <= 2) return launch_j<2, 1>(X, n, d, x, codes, flags, num_cu, s);
+  if (j <= 4) return launch_j<4, 2>(X, n, d, x, codes, flags, num_cu, s);
+  if (j <= 6) return launch_j<6, 4>(X, n, d, x, codes, flags, num_cu, s);
+  if (j <= 8) return launch_j<8, 6>(X, n, d, x, codes, flags, num_cu, s);
+  if (j <= 12) return launch_j<12, 8>(X, n, d, x, codes, flags, num_cu, s);
+  return launch_j<16, 12>(X, n, d, x, codes, flags, num_cu, s);
 }
 
 }  // namespace tqi

@@ -107,6 +107,25 @@ def test_encode_rows_of_many_lengths(tq, o):
         assert np.array_equal(gpu_codes(tq, X, 67), oracle_codes(o, X, 67))
 
 
+@pytest.mark.parametrize("d", [96, 384, 1024])
+def test_encode_many_rows_per_wave(tq, o, d):
+    """Enough rows that every wave encodes several in turn, so each search
+    starts from the previous row's threshold: rows of one scale (a good guess),
+    rows whose scales jump over many binades (the guess is far off, above and
+    below), rows with heavy ties and rows with few non-zeros."""
+    rng = np.random.default_rng(2000 + d)
+    n = 40000
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    kind = rng.integers(0, 4, size=n)
+    X[kind == 1] *= (10.0 ** rng.uniform(-30, 30, size=(int((kind == 1).sum()), 1))).astype(np.float32)
+    X[kind == 2] = np.round(X[kind == 2] * 2) / 2
+    sparse = np.nonzero(kind == 3)[0]
+    X[sparse[:, None], rng.integers(0, d, size=(sparse.size, d // 2))] = 0.0
+    for x in sorted({1, d // 4, oracle.default_x(d), d}):
+        say(f"encode many rows per wave n={n} d={d} x={x}")
+        assert np.array_equal(gpu_codes(tq, X, x), oracle_codes(o, X, x)), f"d={d} x={x}"
+
+
 def test_encode_nonfinite_sets_flag(tq, o):
     rng = np.random.default_rng(7)
     X = rng.standard_normal((6, 64)).astype(np.float32)
