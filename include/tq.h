@@ -158,7 +158,11 @@ typedef struct tq_search_opts {
                         one gives TQ_ERR_INVALID.  Costs a stream sync. */
   int grid;          /* 0 = auto; otherwise the number of workgroups of the
                         scan kernel (tuning / benchmarking) */
-  int qtile;         /* 0 = auto; batched path: queries per workgroup tile */
+  int qtile;         /* 0 = auto; batched path: queries per workgroup tile:
+                        2, 4, 8 or 16 on the popcount engine (at most 8 for
+                        k > 128, 4 for k > 256), 64 or 128 on the matrix
+                        engine, and also 256 there for k <= 16.  A tile of 64
+                        or more with engine AUTO selects the matrix engine. */
   int use_graph;     /* batched path: 1 = replay a captured hipGraph for the
                         batch-size bucket (default when the struct is NULL),
                         0 = launch the kernels directly */
@@ -171,7 +175,7 @@ enum tq_engine {
   TQ_ENGINE_AUTO = 0,     /* the tuned / default choice */
   TQ_ENGINE_POPCOUNT = 1, /* Delta by AND / XOR / popcount on the vector ALUs */
   TQ_ENGINE_MATRIX = 2    /* Delta as a ternary matrix product on the fp4 matrix
-                             cores (exact; k <= 128, query tiles of 16 or 32) */
+                             cores (exact; k <= 128) */
 };
 
 /* k nearest database codes of each of nq query codes.

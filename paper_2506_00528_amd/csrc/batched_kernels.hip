@@ -274,7 +274,10 @@ hipError_t scan_batched_launch(const DbDev &db, const uint32_t *qprep, const Bat
   }
 }
 
-bool mfma_supported(int k, int qtile) { return rows_for_k(k) <= 2 && (qtile == 64 || qtile == 128); }
+bool mfma_supported(int k, int qtile) {
+  if (k <= kGroupMaxK) return qtile == 64 || qtile == 128 || qtile == 256;
+  return rows_for_k(k) <= 2 && (qtile == 64 || qtile == 128);
+}
 
 hipError_t scan_mfma_launch(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile,
                             int grid, uint64_t *partial, hipStream_t s) {

@@ -105,8 +105,9 @@ struct TileStage {
   }
 };
 
+// Two workgroups per CU (their LDS fits) wherever the registers allow it.
 template <int NC, int R, int RB>
-__global__ __launch_bounds__(kMfmaBlock) void scan_mfma_kernel(const uint4 *__restrict__ tiles, int64_t n,
+__global__ __launch_bounds__(kMfmaBlock, R * RB <= 2 ? 2 : 1) void scan_mfma_kernel(const uint4 *__restrict__ tiles, int64_t n,
                                                               const uint32_t *__restrict__ qprep,
                                                               const BatchParams *__restrict__ prm, int k,
                                                               uint64_t *__restrict__ partial) {
@@ -257,6 +258,190 @@ __global__ __launch_bounds__(kMfmaBlock) void scan_mfma_kernel(const uint4 *__re
   }
 }
 
+// ---------------------------------------------------------------------------
+// Small k (k <= 16): lists per 16-lane group, wider query tiles
+// ---------------------------------------------------------------------------
+//
+// The accumulator of one 16x16 product holds, in lane l, rows 4 (l / 16) + i
+// (i = 0..3) of column l % 16: the sixteen lanes of a group carry one query
+// row's scores for sixteen database vectors.  For k <= 16 each query's list
+// lives in exactly those lanes -- entry l % 16 of the list of row
+// 4 (l / 16) + i sits in register i of lane l -- so a list costs a quarter of a
+// register pair, the four groups insert their own candidates at the same
+// time, and a wave can hold 16 RB queries with RB up to 4 (256 queries per
+// workgroup, four times the operand reuse of a 64-query tile).
+
+// 16 keys per group, descending; empty entries are 0.
+struct GroupList {
+  uint64_t v;
+
+  // insert c (this lane's group candidate) where `act`; entries shift down
+  __device__ __forceinline__ void insert(uint64_t c, bool act, int lane) {
+    const uint64_t up = __shfl_up(static_cast<unsigned long long>(v), 1u, 16);
+    const uint64_t prev = (lane & 15) == 0 ? ~0ull : up;
+    const uint64_t nv = (v > c) ? v : ((prev > c) ? c : prev);
+    if (act) v = nv;
+  }
+};
+
+__device__ __forceinline__ uint64_t group_entry(uint64_t v, int gbase, int p) {
+  return __shfl(static_cast<unsigned long long>(v), gbase + p);
+}
+
+template <int NC, int RB>
+__global__ __launch_bounds__(kMfmaBlock, RB <= 2 ? 2 : 1) void scan_mfma_group_kernel(const uint4 *__restrict__ tiles, int64_t n,
+                                                                    const uint32_t *__restrict__ qprep,
+                                                                    const BatchParams *__restrict__ prm, int k,
+                                                                    uint64_t *__restrict__ partial) {
+  constexpr int QW = 16 * RB;
+  constexpr int QT = kMfmaWaves * QW;
+  __shared__ v4i op[2][NC * 4 * 64];
+  const int j = threadIdx.x;
+  const int lane = j & 63;
+  const int wave = j >> 6;
+  const int col = lane & 15;
+  const int grp = lane >> 4;
+  const int gbase = lane & ~15;
+  const int nq = prm->nq, nqt = prm->nqt, parts = prm->parts;
+  const int64_t tpp = prm->tiles_per_part;
+  const int64_t tile_lo = prm->tile_lo, tile_hi = prm->tile_hi;
+  const int items = nqt * parts;
+  const int km1 = k - 1;
+
+  for (int item = blockIdx.x; item < items; item += gridDim.x) {
+    int qt, part;
+    item_coords(item, nqt, &qt, &part);
+    const int q0 = qt * QT + wave * QW;
+    const int nact = max(0, min(QW, nq - q0));
+    const int64_t t0 = tile_lo + static_cast<int64_t>(part) * tpp;
+    const int64_t t1 = min(tile_hi, t0 + tpp);
+
+    v4i a[RB][NC];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      const int qi = rb * 16 + col;
+      const uint32_t *qw = qprep + static_cast<int64_t>(q0 + qi) * (8 * NC);
+#pragma unroll
+      for (int s = 0; s < NC; ++s) {
+        uint32_t nz = 0, ng = 0;
+        if (qi < nact) {
+          nz = qw[4 * s + grp];
+          ng = qw[4 * NC + 4 * s + grp];
+        }
+        a[rb][s] = fp4_operand(nz, ng);
+      }
+    }
+    // list[rb][i] of lane l: entry l % 16 of row 16 rb + 4 (l / 16) + i;
+    // tv[rb][i]: that row's k-th score (rows past the real queries never pass)
+    GroupList list[RB][4];
+    float tv[RB][4];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        list[rb][i].v = 0;
+        tv[rb][i] = (rb * 16 + 4 * grp + i < nact) ? -1e30f : 1e30f;
+      }
+
+    TileStage<NC> sa, sb;
+    auto step = [&](int64_t t, const v4i *cur, v4i *nxt, TileStage<NC> &fill, const TileStage<NC> &ready) {
+      fill.load(tiles, min(t + 2, t1 - 1), j);
+      if (nact > 0) {
+        v4f acc[RB][4];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = v4f{0.f, 0.f, 0.f, 0.f};
+        // K-steps with the next step's four B operands already in flight
+        v4i bq[2][4];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) bq[0][cb] = cur[cb * 64 + lane];
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+          if (s + 1 < NC) {
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) bq[(s + 1) & 1][cb] = cur[((s + 1) * 4 + cb) * 64 + lane];
+          }
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) acc[rb][cb] = mfma_fp4(a[rb][s], bq[s & 1][cb], acc[rb][cb]);
+        }
+        uint64_t rows[RB][4];
+        bool any = false;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            // (the scores are small integers: plain compares, no NaN handling)
+            const bool c = acc[rb][0][i] > tv[rb][i] || acc[rb][1][i] > tv[rb][i] || acc[rb][2][i] > tv[rb][i] ||
+                           acc[rb][3][i] > tv[rb][i];
+            rows[rb][i] = __builtin_amdgcn_ballot_w64(c);
+            any |= rows[rb][i] != 0;
+          }
+        if (any) {
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              if (!rows[rb][i]) continue;
+              GroupList &L = list[rb][i];
+              uint64_t thr = group_entry(L.v, gbase, km1);
+#pragma unroll
+              for (int cb = 0; cb < 4; ++cb) {
+                const int64_t id = t * 64 + cb * 16 + col;
+                const uint64_t key = make_key(static_cast<int32_t>(acc[rb][cb][i]), static_cast<uint32_t>(id));
+                uint64_t m = __ballot(id < n && key > thr);
+                while (m) {
+                  // every group takes its lowest pending lane
+                  const uint32_t mg = static_cast<uint32_t>(m >> gbase) & 0xFFFFu;
+                  const int src = gbase + __builtin_ctz(mg | 0x10000u);
+                  const uint64_t c = __shfl(static_cast<unsigned long long>(key), src & 63);
+                  L.insert(c, mg != 0 && c > thr, lane);
+                  m &= ~__ballot(mg != 0 && lane == src);
+                  thr = group_entry(L.v, gbase, km1);
+                  m &= __ballot(key > thr);
+                }
+              }
+              tv[rb][i] = score_of(thr);
+            }
+          }
+        }
+      }
+      ready.store(nxt, j);
+      __syncthreads();
+    };
+    if (t0 < t1) {
+      sa.load(tiles, t0, j);
+      sb.load(tiles, min(t0 + 1, t1 - 1), j);
+      sa.store(op[0], j);
+      __syncthreads();
+      for (int64_t t = t0; t < t1; t += 2) {
+        step(t, op[0], op[1], sa, sb);
+        if (t + 1 < t1) step(t + 1, op[1], op[0], sb, sa);
+      }
+    }
+
+    // entry p < k of row 16 rb + 4 grp + i is lane 16 grp + p of list[rb][i]
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int qi = rb * 16 + 4 * grp + i;
+        if (qi < nact && col < k)
+          partial[(static_cast<int64_t>(q0 + qi) * parts + part) * k + col] = list[rb][i].v;
+      }
+  }
+}
+
+template <int NC, int RB>
+hipError_t launch_g(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int grid,
+                    uint64_t *partial, hipStream_t s) {
+  hipLaunchKernelGGL((scan_mfma_group_kernel<NC, RB>), dim3(grid), dim3(kMfmaBlock), 0, s, db.tiles, db.n, qprep,
+                     prm, k, partial);
+  return hipGetLastError();
+}
+
 template <int NC, int R, int RB>
 hipError_t launch_m3(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int grid,
                      uint64_t *partial, hipStream_t s) {
@@ -270,6 +455,11 @@ hipError_t launch_m3(const DbDev &db, const uint32_t *qprep, const BatchParams *
 template <int NC>
 hipError_t scan_mfma_launch_nc(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile,
                                int grid, uint64_t *partial, hipStream_t s) {
+  if (k <= kGroupMaxK) {
+    if (qtile == 64) return launch_g<NC, 1>(db, qprep, prm, k, grid, partial, s);
+    if (qtile == 128) return launch_g<NC, 2>(db, qprep, prm, k, grid, partial, s);
+    return launch_g<NC, 4>(db, qprep, prm, k, grid, partial, s);
+  }
   const int r = rows_for_k(k);
   if (qtile == 64) return r == 1 ? launch_m3<NC, 1, 1>(db, qprep, prm, k, grid, partial, s)
                                  : launch_m3<NC, 2, 1>(db, qprep, prm, k, grid, partial, s);

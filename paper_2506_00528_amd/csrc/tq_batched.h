@@ -67,8 +67,9 @@ hipError_t batch_prep_launch(const uint32_t *qcodes, int nq, int bucket, const D
                              int32_t *ids, int32_t *scores, uint32_t *qprep, BatchParams *prm, hipStream_t s);
 hipError_t scan_batched_launch(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile,
                                int grid, uint64_t *partial, hipStream_t s);
-// The same scan on the fp4 matrix cores (mfma_kernels.hip): k <= 128 and
-// query tiles of 64 or 128 per workgroup.
+// The same scan on the fp4 matrix cores (mfma_kernels.hip): k <= 128 with
+// query tiles of 64 or 128 per workgroup, and k <= kGroupMaxK also with 256.
+constexpr int kGroupMaxK = 16;
 bool mfma_supported(int k, int qtile);
 hipError_t scan_mfma_launch(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile,
                             int grid, uint64_t *partial, hipStream_t s);

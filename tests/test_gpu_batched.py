@@ -150,10 +150,12 @@ def test_autotune_then_auto(tq, o, small, tmp_path, monkeypatch):
 # the matrix-core engine (fp4 MFMA): same results, bit for bit
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("k", [1, 10, 64, 65, 100, 128])
-@pytest.mark.parametrize("nq", [1, 3, 17, 100])
-@pytest.mark.parametrize("qtile", [64, 128])
+@pytest.mark.parametrize("k", [1, 10, 16, 17, 64, 65, 100, 128])
+@pytest.mark.parametrize("nq", [1, 3, 17, 100, 300])
+@pytest.mark.parametrize("qtile", [64, 128, 256])
 def test_matrix_vs_oracle(tq, o, small, k, nq, qtile):
+    if qtile == 256 and k > 16:
+        pytest.skip("256-query tiles serve k <= 16")
     say(f"matrix engine small k={k} nq={nq} qtile={qtile}")
     ids, sc = run(tq, small["db"], small["CQ"][:nq], k, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_MATRIX,
                   qtile=qtile)
@@ -178,13 +180,14 @@ def test_matrix_many_queries(tq, o, small):
     assert np.array_equal(sc, es) and np.array_equal(ids, ei)
 
 
+@pytest.mark.parametrize("k", [10, 20])
 @pytest.mark.parametrize("d", [1, 31, 33, 100, 128, 129, 255, 384, 500, 640, 768, 1000, 1024])
-def test_matrix_dims(tq, o, d):
+def test_matrix_dims(tq, o, d, k):
     rng = np.random.default_rng(300 + d)
-    n, x, k = 777, max(1, (2 * d) // 3), 20
+    n, x = 777, max(1, (2 * d) // 3)
     V = o.encode(rng.standard_normal((n, d)).astype(np.float32), x)
     VQ = o.encode(rng.standard_normal((40, d)).astype(np.float32), x)
-    say(f"matrix engine d={d} n={n} x={x}")
+    say(f"matrix engine d={d} n={n} x={x} k={k}")
     db = tq.tq_db_create(dev_codes(o.pack(V)), d, x)
     ids, sc = run(tq, db, o.pack(VQ), k, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_MATRIX)
     ei, es = o.knn(VQ, V, k)
@@ -200,8 +203,8 @@ def test_matrix_heavy_ties(tq, o):
     VQ = np.concatenate([base[:3], o.encode(rng.standard_normal((40, d)).astype(np.float32), x)])
     say("matrix engine heavy ties")
     db = tq.tq_db_create(dev_codes(o.pack(V)), d, x)
-    for k in (1, 10, 100, 128):
-        ids, sc = run(tq, db, o.pack(VQ), k, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_MATRIX)
+    for k, qt in ((1, 64), (10, 128), (16, 256), (100, 64), (128, 128)):
+        ids, sc = run(tq, db, o.pack(VQ), k, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_MATRIX, qtile=qt)
         ei, es = o.knn(VQ, V, k)
         assert np.array_equal(sc, es) and np.array_equal(ids, ei), k
     db.destroy()
@@ -228,5 +231,7 @@ def test_matrix_rejects(tq, small):
         tq.tq_search_knn(small["db"], q, 200, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_MATRIX)
     with pytest.raises(tq.TQError):
         tq.tq_search_knn(small["db"], q, 10, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_MATRIX, qtile=16)
+    with pytest.raises(tq.TQError):  # 256-query tiles serve k <= 16 only
+        tq.tq_search_knn(small["db"], q, 17, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_MATRIX, qtile=256)
     with pytest.raises(tq.TQError):
         tq.tq_search_knn(small["db"], q, 10, path=tq.TQ_PATH_BATCHED, engine=7)
