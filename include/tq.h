@@ -201,6 +201,32 @@ int tq_search_knn(const tq_db *db, const uint32_t *qcodes, int nq, int k, int32_
  * Runs searches on `stream` and waits for them. */
 int tq_autotune(const tq_db *db, int nq_max, const int *ks, int nks, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Refinement of proxy candidates (the search behind the k@n recall of
+ * Sec. 5.3): for each query, order its ncand candidate ids -- typically the
+ * ids of tq_search_knn with k = n > the wanted k -- by the scalar product of
+ * the original float vectors, and keep the best k.  For l2-normalised
+ * embeddings (Sec. 1.1) that is the l2 order.  Products and sums are in
+ * double precision; scores are written as doubles.  Order: larger score
+ * first, the lower id on equal scores.
+ *
+ *   X       device pointer, n x d float32, row-major: the database vectors
+ *           (the same floats that were encoded).
+ *   Q       device pointer, nq x d float32: the queries.
+ *   cand    device pointer, nq x ncand int32: candidate ids; an id outside
+ *           [0, n) is ignored.  Ids of one query should be distinct.
+ *   ids     device pointer, nq x k int32 (written); -1 where a query has
+ *           fewer than k valid candidates.
+ *   scores  device pointer, nq x k double (written); -infinity where ids
+ *           holds -1.
+ *
+ * Requires n >= 1, 1 <= d <= TQ_MAX_D, nq >= 0, 1 <= ncand <= TQ_MAX_RERANK,
+ * 1 <= k <= ncand; else TQ_ERR_INVALID before anything is queued.
+ * Asynchronous on `stream`; reads each candidate row once (4d bytes). */
+#define TQ_MAX_RERANK 1024
+int tq_rerank(const float *X, int64_t n, int d, const float *Q, int nq, const int32_t *cand, int ncand, int k,
+              int32_t *ids, double *scores, void *stream);
+
 /* Debugging / parity aid: the full nq x n matrix of Delta(q_i, s_j)
  * (int32, row-major, device pointer), computed with the same device code as
  * the search.  Asynchronous on `stream`. */

@@ -5,7 +5,9 @@ CPU-baseline leg may import this package.  It shares no code with the GPU
 library and never imports it.
 
 The arithmetic lives in ``oracle.c`` (plain C + OpenMP, built with gcc); this
-module only marshals numpy arrays, plus a few pure-Python definitions:
+module only marshals numpy arrays (encode, pack, unpack, delta, knn, and the
+refinement of proxy candidates with the float vectors, rerank), plus a few
+pure-Python definitions:
 
 * ``default_x(d)``     -- the x maximising the vertex count C(d,x)*2^x
                           (Sec. 5.1.1), by brute force over all x with exact
@@ -52,6 +54,7 @@ def load(path: str | None = None):
     lib.oracle_unpack.argtypes = [vp, i64, i32, vp]
     lib.oracle_delta.argtypes = [vp, i64, vp, i64, i32, vp]
     lib.oracle_knn.argtypes = [vp, i64, vp, i64, i32, i32, vp, vp]
+    lib.oracle_rerank.argtypes = [vp, i64, i32, vp, i64, vp, i32, i32, vp, vp]
     lib.oracle_num_threads.restype = i32
     lib.oracle_set_num_threads.argtypes = [i32]
     if path is None:
@@ -149,6 +152,30 @@ class Oracle:
         return ids, scores
 
 
+    # -- refinement of proxy candidates (Sec. 5.3 k@n) ---------------------
+    def rerank(self, X: np.ndarray, Q: np.ndarray, cand: np.ndarray, k: int):
+        """The k best of each query's candidate ids by the double-precision
+        scalar product of the float vectors (ties: lower id); ids outside
+        [0, n) are skipped, missing results are id -1, score -inf."""
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        Q = np.ascontiguousarray(Q, dtype=np.float32)
+        cand = np.ascontiguousarray(cand, dtype=np.int32)
+        if Q.ndim == 1:
+            Q = Q[None, :]
+        if cand.ndim == 1:
+            cand = cand[None, :]
+        if Q.shape[1] != X.shape[1] or cand.shape[0] != Q.shape[0]:
+            raise ValueError("shape mismatch")
+        nq, ncand = cand.shape
+        ids = np.empty((nq, k), dtype=np.int32)
+        scores = np.empty((nq, k), dtype=np.float64)
+        rc = self.lib.oracle_rerank(X.ctypes.data, X.shape[0], X.shape[1], Q.ctypes.data, nq, cand.ctypes.data,
+                                    ncand, int(k), ids.ctypes.data, scores.ctypes.data)
+        if rc != 0:
+            raise OracleError(rc, "rerank")
+        return ids, scores
+
+
 # -- pure-Python definitions ------------------------------------------------
 
 def vertex_count(d: int, x: int) -> int:
@@ -196,3 +223,7 @@ def delta(Q, V):
 
 def knn(Q, V, k):
     return default().knn(Q, V, k)
+
+
+def rerank(X, Q, cand, k):
+    return default().rerank(X, Q, cand, k)

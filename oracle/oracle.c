@@ -22,6 +22,9 @@
  *   knn    : exhaustive kNN in the proxy space (problem statement of Sec. 1.1
  *            and Table 1; "closest n" of Sec. 5.3): score every database
  *            vector, order all of them, keep the first k.
+ *   rerank : the n proxy candidates of a query ordered by the scalar product
+ *            of the original float vectors (the search that the k@n recall of
+ *            Sec. 5.3 measures), the first k kept.
  *
  * Readings taken where the paper is silent (each is listed in the design notes):
  *   - equal magnitudes at the x-th place: the lower coordinate index wins;
@@ -290,4 +293,90 @@ int oracle_knn(const int8_t *Q, int64_t nq, const int8_t *V, int64_t n, int d, i
   free(all);
   free(tmp);
   return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Refinement of proxy candidates with the original vectors                 */
+/* ------------------------------------------------------------------------ */
+/*
+ * Sec. 5.3 measures k@n recall: how many of the k true nearest neighbours
+ * are among the n nearest in the proxy space.  The search that this protects
+ * takes those n proxy candidates and orders them by the original similarity.
+ * For l2-normalised vectors (Sec. 1.1) the nearest in l2 distance are the
+ * largest scalar products, so each candidate is scored with the double
+ * precision scalar product of the float vectors (products and sums in
+ * double, in coordinate order), and the k best are kept: larger score first,
+ * the lower id on equal scores.  A candidate id outside [0, n) is skipped;
+ * missing results are written as id -1 with score -infinity.
+ */
+typedef struct {
+  double score;
+  int32_t id;
+} refined_t;
+
+static int refined_before(refined_t a, refined_t b) {
+#if ORACLE_MUTANT == 6
+  if (a.score != b.score) return a.score < b.score; /* planted: the worst first */
+#else
+  if (a.score != b.score) return a.score > b.score;
+#endif
+#if ORACLE_MUTANT == 7
+  return a.id > b.id; /* planted: ties to the higher id */
+#else
+  return a.id < b.id;
+#endif
+}
+
+static void merge_sort_refined(refined_t *s, refined_t *tmp, int lo, int hi) {
+  if (hi - lo < 2) return;
+  int mid = lo + (hi - lo) / 2;
+  merge_sort_refined(s, tmp, lo, mid);
+  merge_sort_refined(s, tmp, mid, hi);
+  int i = lo, j = mid, o = lo;
+  while (i < mid && j < hi) {
+    if (refined_before(s[j], s[i]))
+      tmp[o++] = s[j++];
+    else
+      tmp[o++] = s[i++];
+  }
+  while (i < mid) tmp[o++] = s[i++];
+  while (j < hi) tmp[o++] = s[j++];
+  for (o = lo; o < hi; ++o) s[o] = tmp[o];
+}
+
+int oracle_rerank(const float *X, int64_t n, int d, const float *Q, int64_t nq, const int32_t *cand, int ncand,
+                  int k, int32_t *ids, double *scores) {
+  if (n < 1 || d < 1 || nq < 0 || ncand < 1 || k < 1 || k > ncand) return ORACLE_EINVAL;
+  int rc = 0;
+#pragma omp parallel for schedule(dynamic) reduction(min : rc)
+  for (int64_t q = 0; q < nq; ++q) {
+    refined_t *all = (refined_t *)malloc(sizeof(refined_t) * (size_t)ncand);
+    refined_t *tmp = (refined_t *)malloc(sizeof(refined_t) * (size_t)ncand);
+    if (!all || !tmp) {
+      free(all);
+      free(tmp);
+      rc = ORACLE_ENOMEM;
+      continue;
+    }
+    const float *qv = Q + q * (int64_t)d;
+    int m = 0;
+    for (int c = 0; c < ncand; ++c) {
+      const int32_t id = cand[q * (int64_t)ncand + c];
+      if (id < 0 || (int64_t)id >= n) continue;
+      const float *xv = X + (int64_t)id * d;
+      double s = 0.0;
+      for (int i = 0; i < d; ++i) s += (double)qv[i] * (double)xv[i];
+      all[m].score = s;
+      all[m].id = id;
+      ++m;
+    }
+    merge_sort_refined(all, tmp, 0, m);
+    for (int j = 0; j < k; ++j) {
+      ids[q * k + j] = j < m ? all[j].id : -1;
+      scores[q * k + j] = j < m ? all[j].score : -INFINITY;
+    }
+    free(all);
+    free(tmp);
+  }
+  return rc;
 }

@@ -368,6 +368,23 @@ int tq_search_knn(const tq_db *cdb, const uint32_t *qcodes, int nq, int k, int32
   return search_plain(db, qcodes, nq, k, ids, scores, opts ? opts->grid : 0, s);
 }
 
+int tq_rerank(const float *X, int64_t n, int d, const float *Q, int nq, const int32_t *cand, int ncand, int k,
+              int32_t *ids, double *scores, void *stream) {
+  clear_error();
+  if (!X || !Q || !cand || !ids || !scores) return fail(TQ_ERR_INVALID, "null pointer argument");
+  if (n < 1) return fail(TQ_ERR_INVALID, "n=%lld < 1", (long long)n);
+  if (d < 1 || d > TQ_MAX_D) return fail(TQ_ERR_INVALID, "d=%d outside [1, %d]", d, TQ_MAX_D);
+  if (nq < 0) return fail(TQ_ERR_INVALID, "nq=%d < 0", nq);
+  if (ncand < 1 || ncand > TQ_MAX_RERANK)
+    return fail(TQ_ERR_INVALID, "ncand=%d outside [1, %d]", ncand, TQ_MAX_RERANK);
+  if (k < 1 || k > ncand) return fail(TQ_ERR_INVALID, "k=%d outside [1, ncand=%d]", k, ncand);
+  static_assert(TQ_MAX_RERANK == tqi::kMaxRerank, "candidate limit");
+  if (nq == 0) return TQ_OK;
+  hipError_t e = tqi::rerank_launch(X, n, d, Q, nq, cand, ncand, k, ids, scores, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "rerank launch");
+  return TQ_OK;
+}
+
 int tq_delta_dump(const tq_db *db, const uint32_t *qcodes, int nq, int32_t *delta, void *stream) {
   clear_error();
   if (!db || !qcodes || !delta) return fail(TQ_ERR_INVALID, "null db, qcodes or delta");

@@ -94,4 +94,10 @@ hipError_t merge_launch(const uint64_t *partial, int nq, int nlists, int k, int3
 hipError_t delta_dump_launch(const DbDev &db, const uint32_t *qcodes, int nq, int32_t *out,
                              hipStream_t s);
 
+// rerank.hip: the k best of each query's ncand candidate rows of X (n x d
+// floats) by the double-precision scalar product with the query (nq x d).
+constexpr int kMaxRerank = 1024;  // candidates per query
+hipError_t rerank_launch(const float *X, int64_t n, int d, const float *Q, int nq, const int32_t *cand, int ncand,
+                         int k, int32_t *ids, double *scores, hipStream_t s);
+
 }  // namespace tqi

@@ -43,7 +43,7 @@ EXPORTS = (
     "tq_status_str", "tq_last_error", "tq_version", "tq_code_words", "tq_encode", "tq_db_create",
     "tq_db_export", "tq_db_info", "tq_db_destroy", "tq_search_knn", "tq_autotune", "tq_delta_dump", "tq_sync",
     "tq_serve_create", "tq_serve_submit", "tq_serve_poll", "tq_serve_wait", "tq_serve_cancel",
-    "tq_serve_stats", "tq_serve_destroy", "tq_timing_enable", "tq_timing_read",
+    "tq_serve_stats", "tq_serve_destroy", "tq_timing_enable", "tq_timing_read", "tq_rerank",
 )
 
 
@@ -98,6 +98,7 @@ def lib(path: Optional[str] = None):
         "tq_search_knn": ([vp, vp, i32, i32, vp, vp, P(tq_search_opts), vp], i32),
         "tq_autotune": ([vp, i32, P(i32), i32, vp], i32),
         "tq_delta_dump": ([vp, vp, i32, vp, vp], i32),
+        "tq_rerank": ([vp, i64, i32, vp, i32, vp, i32, i32, vp, vp, vp], i32),
         "tq_sync": ([vp], i32),
         "tq_serve_create": ([vp, P(tq_serve_cfg), P(vp)], i32),
         "tq_serve_submit": ([vp, vp, i32, i32, P(u64)], i32),
@@ -281,6 +282,29 @@ def tq_delta_dump(db: tq_db, qcodes: torch.Tensor, stream=None) -> torch.Tensor:
         _check(lib().tq_delta_dump(db.handle, _dev(qcodes, "qcodes", torch.int32), nq,
                                    _dev(out, "delta", torch.int32), _stream(qcodes, stream)), "tq_delta_dump")
     return out
+
+
+TQ_MAX_RERANK = 1024
+
+
+def tq_rerank(X: torch.Tensor, Q: torch.Tensor, cand: torch.Tensor, k: int, ids: Optional[torch.Tensor] = None,
+              scores: Optional[torch.Tensor] = None, stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """The k best of each query's candidate ids by the float scalar product
+    (double precision); see tq.h.  X: n x d float32, Q: nq x d float32,
+    cand: nq x ncand int32, all on the GPU."""
+    n, d = int(X.shape[0]), int(X.shape[1])
+    nq, ncand = int(cand.shape[0]), int(cand.shape[1])
+    if Q.shape[0] != nq or Q.shape[1] != d:
+        raise ValueError("Q must be nq x d")
+    with torch.cuda.device(X.device):
+        if ids is None:
+            ids = torch.empty((nq, k), dtype=torch.int32, device=X.device)
+        if scores is None:
+            scores = torch.empty((nq, k), dtype=torch.float64, device=X.device)
+        _check(lib().tq_rerank(_dev(X, "X", torch.float32), n, d, _dev(Q, "Q", torch.float32), nq,
+                               _dev(cand, "cand", torch.int32), ncand, int(k), _dev(ids, "ids", torch.int32),
+                               _dev(scores, "scores", torch.float64), _stream(X, stream)), "tq_rerank")
+    return ids, scores
 
 
 def tq_timing_enable(on: bool = True) -> None:

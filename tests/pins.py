@@ -301,9 +301,70 @@ def check_knn_shard_merge(o, seed=11):
         assert np.array_equal(ci[q][order], full_i[q]) and np.array_equal(cs[q][order], full_s[q])
 
 
+# ---------------------------------------------------------------------------
+# refinement of proxy candidates with the float vectors (Sec. 5.3 k@n)
+# ---------------------------------------------------------------------------
+
+def check_rerank_l2_order(o, seed=12):
+    """With every id as a candidate and vectors of equal norm, the refined
+    order is the order of l2 distance (Sec. 1.1: for normalised data the
+    nearest in l2 have the largest scalar products).  Ternary {x,d} vertices
+    as floats have norm^2 = x exactly and l2^2 = 2x - 2<q,v>, so the squared
+    distances computed coordinate by coordinate below are exact."""
+    rng = np.random.default_rng(seed)
+    d, x, n = 24, 9, 300
+    V = o.encode(rng.standard_normal((n, d)).astype(np.float32), x).astype(np.float32)
+    Qv = o.encode(rng.standard_normal((6, d)).astype(np.float32), x).astype(np.float32)
+    cand = np.tile(np.arange(n, dtype=np.int32), (6, 1))
+    k = 25
+    ids, sc = o.rerank(V, Qv, cand, k)
+    for q in range(6):
+        dist = [sum((float(Qv[q, i]) - float(V[j, i])) ** 2 for i in range(d)) for j in range(n)]
+        order = sorted(range(n), key=lambda j: (dist[j], j))[:k]
+        assert ids[q].tolist() == order, q
+        assert np.array_equal(sc[q], np.array([x - dist[j] / 2 for j in order])), q
+
+
+def check_rerank_invariants(o, seed=13):
+    """Results are candidates, in (score desc, id asc) order, each score the
+    scalar product of its pair; the candidate order does not matter; ids
+    outside [0, n) are skipped and missing results are (-1, -inf)."""
+    rng = np.random.default_rng(seed)
+    n, d, nq, ncand, k = 400, 37, 5, 60, 12
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    X[7] = X[3]  # an exact tie: equal rows give equal scores
+    Q = rng.standard_normal((nq, d)).astype(np.float32)
+    cand = np.stack([rng.permutation(n)[:ncand] for _ in range(nq)]).astype(np.int32)
+    cand[:, 0], cand[:, 1] = 3, 7
+    ids, sc = o.rerank(X, Q, cand, k)
+    for q in range(nq):
+        assert set(ids[q].tolist()) <= set(cand[q].tolist())
+        for j in range(k):
+            ref = float(np.dot(Q[q].astype(np.float64), X[ids[q, j]].astype(np.float64)))
+            assert abs(sc[q, j] - ref) <= 1e-12 * max(1.0, abs(ref))
+            if j:
+                assert sc[q, j - 1] > sc[q, j] or (sc[q, j - 1] == sc[q, j] and ids[q, j - 1] < ids[q, j])
+        # nothing left out beats the k-th
+        left = [c for c in cand[q] if c not in set(ids[q].tolist())]
+        for c in left:
+            s = float(np.dot(Q[q].astype(np.float64), X[c].astype(np.float64)))
+            assert (s, -c) < (sc[q, k - 1], -ids[q, k - 1])
+        pos3, pos7 = list(ids[q]).index(3) if 3 in ids[q] else None, list(ids[q]).index(7) if 7 in ids[q] else None
+        if pos3 is not None and pos7 is not None:
+            assert pos3 < pos7, "equal scores: the lower id first"
+    perm = np.stack([rng.permutation(ncand) for _ in range(nq)])
+    ids2, sc2 = o.rerank(X, Q, np.take_along_axis(cand, perm, 1), k)
+    assert np.array_equal(ids, ids2) and np.array_equal(sc, sc2)
+    bad = cand.copy()
+    bad[:, 2:] = -1
+    bad[:, 1] = n  # outside [0, n)
+    ids3, sc3 = o.rerank(X, Q, bad, 3)
+    assert np.all(ids3[:, 0] == 3) and np.all(ids3[:, 1:] == -1) and np.all(np.isneginf(sc3[:, 1:]))
+
+
 ALL_CHECKS = [
     check_table3_encode, check_enumeration_argmax, check_fig2_cuboctahedron, check_special_cases,
     check_invariants, check_ties_and_zeros, check_table3_pack, check_pack_layout, check_table3_delta,
     check_delta_identities, check_delta_one_bit_hamming, check_delta_bitwise, check_knn_bruteforce,
-    check_knn_ties, check_knn_shard_merge,
+    check_knn_ties, check_knn_shard_merge, check_rerank_l2_order, check_rerank_invariants,
 ]

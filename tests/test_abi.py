@@ -65,3 +65,19 @@ def test_host_validation_without_gpu(tq):
     assert L.tq_db_destroy(None) == tq.TQ_OK
     assert L.tq_serve_destroy(None) == tq.TQ_OK
     assert L.tq_timing_read(7, None, None, 0) == tq.TQ_ERR_INVALID
+
+
+def test_rerank_host_validation_without_gpu(tq):
+    L = tq.lib()
+    p = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
+    assert L.tq_rerank(None, 10, 8, p, 1, p, 4, 2, p, p, None) == tq.TQ_ERR_INVALID
+    assert L.tq_rerank(p, 0, 8, p, 1, p, 4, 2, p, p, None) == tq.TQ_ERR_INVALID
+    assert L.tq_rerank(p, 10, 0, p, 1, p, 4, 2, p, p, None) == tq.TQ_ERR_INVALID
+    assert L.tq_rerank(p, 10, tq.TQ_MAX_D + 1, p, 1, p, 4, 2, p, p, None) == tq.TQ_ERR_INVALID
+    assert L.tq_rerank(p, 10, 8, p, -1, p, 4, 2, p, p, None) == tq.TQ_ERR_INVALID
+    assert L.tq_rerank(p, 10, 8, p, 1, p, 0, 1, p, p, None) == tq.TQ_ERR_INVALID
+    assert L.tq_rerank(p, 10, 8, p, 1, p, tq.TQ_MAX_RERANK + 1, 2, p, p, None) == tq.TQ_ERR_INVALID
+    assert L.tq_rerank(p, 10, 8, p, 1, p, 4, 5, p, p, None) == tq.TQ_ERR_INVALID
+    assert "k=5" in tq.last_error()
+    assert L.tq_rerank(p, 10, 8, p, 1, p, 4, 0, p, p, None) == tq.TQ_ERR_INVALID
+    assert L.tq_rerank(p, 10, 8, p, 0, p, 4, 2, p, p, None) == tq.TQ_OK  # nothing to do

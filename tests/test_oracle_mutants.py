@@ -15,6 +15,8 @@ MUTANTS = {
     3: "Delta drops the disagreeing terms",
     4: "top-k ties go to the higher id",
     5: "bit planes packed most-significant-bit first",
+    6: "rerank keeps the worst candidates",
+    7: "rerank ties go to the higher id",
 }
 
 
