@@ -8,18 +8,20 @@
 // float vectors, products and sums in double precision, and the k best are
 // kept (larger first; the lower id on equal scores).
 //
-// One workgroup per query.  Each lane holds the query coordinates l, l + 64,
-// ...; a wave scores four candidates at a time (the four rows' loads in
-// flight together, each row read as coalesced 256-byte runs), reduces each
-// across the wave, and parks (score, id) in LDS; a bitonic sort over the
-// padded candidate list then puts the best first.  Gather-bound: every
-// candidate row is read once (4d bytes).
+// One workgroup of eight waves per query (so that even a hundred queries
+// keep most SIMDs busy).  The candidate ids are first staged in LDS with one
+// coalesced read; each lane holds the query coordinates l, l + 64, ...; a
+// wave scores four candidates at a time (the four rows' loads in flight
+// together, each row read as coalesced 256-byte runs), reduces each across
+// the wave, and parks (score, id) in LDS; a bitonic sort over the padded
+// candidate list then puts the best first.  Gather-bound: every candidate row
+// is read once (4d bytes).
 #include "tq_internal.h"
 
 namespace tqi {
 namespace {
 
-constexpr int kRerankWaves = 4;
+constexpr int kRerankWaves = 8;
 constexpr int kRerankBlock = 64 * kRerankWaves;
 constexpr int kRerankBatch = 4;  // candidates in flight per wave
 
@@ -44,14 +46,17 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_kernel(const float *__res
     qv[j] = i < d ? Q[q * d + i] : 0.0f;
   }
   const int32_t *cq = cand + q * ncand;
+  for (int c = threadIdx.x; c < P; c += kRerankBlock) {
+    const int32_t id = c < ncand ? cq[c] : -1;
+    sid[c] = (id < 0 || id >= n) ? -1 : id;
+  }
+  __syncthreads();
   for (int c0 = wave * kRerankBatch; c0 < P; c0 += kRerankWaves * kRerankBatch) {
     int32_t cid[kRerankBatch];
     float xv[kRerankBatch][J];
 #pragma unroll
     for (int b = 0; b < kRerankBatch; ++b) {
-      const int c = c0 + b;
-      int32_t id = c < ncand ? cq[c] : -1;
-      if (id < 0 || id >= n) id = -1;
+      const int id = sid[c0 + b];
       cid[b] = id;
       const float *xr = X + static_cast<int64_t>(id < 0 ? 0 : id) * d;
 #pragma unroll
@@ -67,10 +72,9 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_kernel(const float *__res
       for (int j = 0; j < J; ++j) acc = fma(static_cast<double>(qv[j]), static_cast<double>(xv[b][j]), acc);
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-      const int c = c0 + b;
-      if (lane == 0 && c < P) {
-        sc[c] = cid[b] >= 0 ? acc : -__builtin_huge_val();
-        sid[c] = cid[b] >= 0 ? cid[b] : INT32_MAX;
+      if (lane == 0) {
+        sc[c0 + b] = cid[b] >= 0 ? acc : -__builtin_huge_val();
+        sid[c0 + b] = cid[b] >= 0 ? cid[b] : INT32_MAX;
       }
     }
   }
@@ -105,7 +109,7 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_kernel(const float *__res
 template <int J>
 hipError_t launch_r(const float *X, int64_t n, int d, const float *Q, int nq, const int32_t *cand, int ncand,
                     int k, int32_t *ids, double *scores, hipStream_t s) {
-  int P = 1;
+  int P = kRerankBatch;  // a power of two covering the candidates, whole batches
   while (P < ncand) P <<= 1;
   hipLaunchKernelGGL((rerank_kernel<J>), dim3(static_cast<unsigned>(nq)), dim3(kRerankBlock), 0, s, X, n, d, Q,
                      cand, ncand, P, k, ids, scores);
