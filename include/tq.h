@@ -202,6 +202,27 @@ int tq_search_knn(const tq_db *db, const uint32_t *qcodes, int nq, int k, int32_
 int tq_autotune(const tq_db *db, int nq_max, const int *ks, int nks, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Masked addition (Sec. 5.1.2; the asymmetric variant of Sec. 6): k nearest
+ * database codes of each of nq FLOAT queries, scored without encoding the
+ * query: score(q, v) = sum of q_i where v+ is set - sum of q_i where v- is
+ * set (the scalar product of q with the ternary v).  The two sums are taken
+ * in double precision and rounded once to float; results are ordered by that
+ * float score (larger first), the lower id on equal scores.  One database
+ * pass per query, like TQ_PATH_PLAIN.
+ *
+ *   Q       device pointer, nq x d float32 (the database's d).
+ *   ids     device pointer, nq x k int32 (written).
+ *   scores  device pointer, nq x k float32 (written).
+ *   opts    may be NULL; only opts->grid is used.
+ *
+ * Requires 1 <= nq, 1 <= k <= min(n, TQ_MAX_K).  Asynchronous on `stream`.
+ * The summation order differs from a sequential one, so a score can differ
+ * from the sequentially summed one in the last float bit when that sum lies
+ * within ~1e-12 (relative) of a float rounding boundary. */
+int tq_search_masked(const tq_db *db, const float *Q, int nq, int k, int32_t *ids, float *scores,
+                     const tq_search_opts *opts, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Refinement of proxy candidates (the search behind the k@n recall of
  * Sec. 5.3): for each query, order its ncand candidate ids -- typically the
  * ids of tq_search_knn with k = n > the wanted k -- by the scalar product of
@@ -307,7 +328,8 @@ int tq_serve_destroy(tq_server *srv);
 int tq_timing_enable(int enable);
 
 /* Sum of the timed scan-kernel durations since the last reset, and the number
- * of launches, for kernel family `which` (0 = plain scan, 1 = batched scan).
+ * of launches, for kernel family `which` (0 = plain scan, 1 = batched scan,
+ * 2 = masked-addition scan).
  * Waits for the recorded events.  reset != 0 clears the counters. */
 int tq_timing_read(int which, double *total_ms, int64_t *launches, int reset);
 

@@ -5,9 +5,10 @@ CPU-baseline leg may import this package.  It shares no code with the GPU
 library and never imports it.
 
 The arithmetic lives in ``oracle.c`` (plain C + OpenMP, built with gcc); this
-module only marshals numpy arrays (encode, pack, unpack, delta, knn, and the
-refinement of proxy candidates with the float vectors, rerank), plus a few
-pure-Python definitions:
+module only marshals numpy arrays (encode, pack, unpack, delta, knn, the
+refinement of proxy candidates with the float vectors, rerank, and the
+masked-addition search of float queries against ternary vectors,
+masked_knn), plus a few pure-Python definitions:
 
 * ``default_x(d)``     -- the x maximising the vertex count C(d,x)*2^x
                           (Sec. 5.1.1), by brute force over all x with exact
@@ -55,6 +56,7 @@ def load(path: str | None = None):
     lib.oracle_delta.argtypes = [vp, i64, vp, i64, i32, vp]
     lib.oracle_knn.argtypes = [vp, i64, vp, i64, i32, i32, vp, vp]
     lib.oracle_rerank.argtypes = [vp, i64, i32, vp, i64, vp, i32, i32, vp, vp]
+    lib.oracle_masked_knn.argtypes = [vp, i64, vp, i64, i32, i32, vp, vp, vp]
     lib.oracle_num_threads.restype = i32
     lib.oracle_set_num_threads.argtypes = [i32]
     if path is None:
@@ -176,6 +178,28 @@ class Oracle:
         return ids, scores
 
 
+    # -- masked addition: float query vs ternary database (Sec. 5.1.2, 6) --
+    def masked_knn(self, Q: np.ndarray, V: np.ndarray, k: int):
+        """Top-k of each float query against ternary vectors V by masked
+        addition: ids, float scores (the double sums rounded once) and the
+        double sums themselves."""
+        Q = np.ascontiguousarray(Q, dtype=np.float32)
+        V = np.ascontiguousarray(V, dtype=np.int8)
+        if Q.ndim == 1:
+            Q = Q[None, :]
+        if Q.shape[1] != V.shape[1]:
+            raise ValueError("dimension mismatch")
+        nq = Q.shape[0]
+        ids = np.empty((nq, k), dtype=np.int32)
+        scores = np.empty((nq, k), dtype=np.float32)
+        exact = np.empty((nq, k), dtype=np.float64)
+        rc = self.lib.oracle_masked_knn(Q.ctypes.data, nq, V.ctypes.data, V.shape[0], Q.shape[1], int(k),
+                                        ids.ctypes.data, scores.ctypes.data, exact.ctypes.data)
+        if rc != 0:
+            raise OracleError(rc, "masked_knn")
+        return ids, scores, exact
+
+
 # -- pure-Python definitions ------------------------------------------------
 
 def vertex_count(d: int, x: int) -> int:
@@ -227,3 +251,7 @@ def knn(Q, V, k):
 
 def rerank(X, Q, cand, k):
     return default().rerank(X, Q, cand, k)
+
+
+def masked_knn(Q, V, k):
+    return default().masked_knn(Q, V, k)

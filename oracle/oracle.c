@@ -25,6 +25,8 @@
  *   rerank : the n proxy candidates of a query ordered by the scalar product
  *            of the original float vectors (the search that the k@n recall of
  *            Sec. 5.3 measures), the first k kept.
+ *   masked : exhaustive kNN of a float query against the ternary vectors by
+ *            masked addition (Sec. 5.1.2; the asymmetric variant of Sec. 6).
  *
  * Readings taken where the paper is silent (each is listed in the design notes):
  *   - equal magnitudes at the x-th place: the lower coordinate index wins;
@@ -379,4 +381,89 @@ int oracle_rerank(const float *X, int64_t n, int d, const float *Q, int64_t nq, 
     free(tmp);
   }
   return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Masked addition: a float query against ternary database vectors          */
+/* ------------------------------------------------------------------------ */
+/*
+ * Sec. 5.1.2: the scalar product of a ternary v with any vector w is the sum
+ * of w over the coordinates where v+ is set minus the sum of w where v- is
+ * set (no multiplications); Sec. 6 notes that comparing the ternary database
+ * with the original float query is the more accurate variant.  The two sums
+ * are taken here in double precision, coordinate by coordinate in index
+ * order; the score is their difference rounded once to float, and the k
+ * largest scores are kept (the lower id on equal float scores).  The exact
+ * double difference is also returned, for tolerance checks.
+ */
+typedef struct {
+  float score;
+  double exact;
+  int32_t id;
+} masked_t;
+
+static int masked_before(masked_t a, masked_t b) {
+  if (a.score != b.score) return a.score > b.score;
+  return a.id < b.id;
+}
+
+static void merge_sort_masked(masked_t *s, masked_t *tmp, int64_t lo, int64_t hi) {
+  if (hi - lo < 2) return;
+  int64_t mid = lo + (hi - lo) / 2;
+  merge_sort_masked(s, tmp, lo, mid);
+  merge_sort_masked(s, tmp, mid, hi);
+  int64_t i = lo, j = mid, o = lo;
+  while (i < mid && j < hi) {
+    if (masked_before(s[j], s[i]))
+      tmp[o++] = s[j++];
+    else
+      tmp[o++] = s[i++];
+  }
+  while (i < mid) tmp[o++] = s[i++];
+  while (j < hi) tmp[o++] = s[j++];
+  for (o = lo; o < hi; ++o) s[o] = tmp[o];
+}
+
+static double masked_addition(const float *w, const int8_t *v, int d) {
+  double plus = 0.0, minus = 0.0;
+  for (int i = 0; i < d; ++i) {
+#if ORACLE_MUTANT == 8
+    if (v[i] != 0) plus += (double)w[i]; /* planted: the sign of v ignored */
+#else
+    if (v[i] > 0) plus += (double)w[i];
+    if (v[i] < 0) minus += (double)w[i];
+#endif
+  }
+  return plus - minus;
+}
+
+int oracle_masked_knn(const float *Q, int64_t nq, const int8_t *V, int64_t n, int d, int k, int32_t *ids,
+                      float *scores, double *exact) {
+  if (nq < 0 || n < 1 || n > INT32_MAX || d < 1 || k < 1 || k > n) return ORACLE_EINVAL;
+  masked_t *all = (masked_t *)malloc(sizeof(masked_t) * (size_t)n);
+  masked_t *tmp = (masked_t *)malloc(sizeof(masked_t) * (size_t)n);
+  if (!all || !tmp) {
+    free(all);
+    free(tmp);
+    return ORACLE_ENOMEM;
+  }
+  for (int64_t q = 0; q < nq; ++q) {
+    const float *qv = Q + q * (int64_t)d;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      const double s = masked_addition(qv, V + i * (int64_t)d, d);
+      all[i].exact = s;
+      all[i].score = (float)s;
+      all[i].id = (int32_t)i;
+    }
+    merge_sort_masked(all, tmp, 0, n);
+    for (int j = 0; j < k; ++j) {
+      ids[q * k + j] = all[j].id;
+      scores[q * k + j] = all[j].score;
+      exact[q * k + j] = all[j].exact;
+    }
+  }
+  free(all);
+  free(tmp);
+  return 0;
 }

@@ -104,9 +104,9 @@ namespace {
 struct Timing {
   std::mutex mu;
   std::vector<hipEvent_t> pool;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[2];
-  double total_ms[2] = {0, 0};
-  int64_t launches[2] = {0, 0};
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[kTimeFamilies];
+  double total_ms[kTimeFamilies] = {};
+  int64_t launches[kTimeFamilies] = {};
 };
 Timing g_timing;
 std::atomic<int> g_timing_on{0};
@@ -368,6 +368,20 @@ int tq_search_knn(const tq_db *cdb, const uint32_t *qcodes, int nq, int k, int32
   return search_plain(db, qcodes, nq, k, ids, scores, opts ? opts->grid : 0, s);
 }
 
+int tq_search_masked(const tq_db *cdb, const float *Q, int nq, int k, int32_t *ids, float *scores,
+                     const tq_search_opts *opts, void *stream) {
+  clear_error();
+  tq_db *db = const_cast<tq_db *>(cdb);
+  if (!db) return fail(TQ_ERR_INVALID, "null db");
+  if (!Q || !ids || !scores) return fail(TQ_ERR_INVALID, "null Q, ids or scores");
+  if (nq < 1) return fail(TQ_ERR_INVALID, "nq=%d < 1", nq);
+  if (k < 1 || k > TQ_MAX_K || k > db->dev.n)
+    return fail(TQ_ERR_INVALID, "k=%d outside [1, min(n=%lld, %d)]", k, (long long)db->dev.n, TQ_MAX_K);
+  DeviceGuard g(db->device);
+  std::lock_guard<std::mutex> l(db->mu);
+  return search_masked(db, Q, nq, k, ids, scores, opts ? opts->grid : 0, static_cast<hipStream_t>(stream));
+}
+
 int tq_rerank(const float *X, int64_t n, int d, const float *Q, int nq, const int32_t *cand, int ncand, int k,
               int32_t *ids, double *scores, void *stream) {
   clear_error();
@@ -414,7 +428,7 @@ int tq_timing_enable(int enable) {
 
 int tq_timing_read(int which, double *total_ms, int64_t *launches, int reset) {
   clear_error();
-  if (which < 0 || which > 1) return fail(TQ_ERR_INVALID, "timing family %d", which);
+  if (which < 0 || which >= kTimeFamilies) return fail(TQ_ERR_INVALID, "timing family %d", which);
   std::lock_guard<std::mutex> g(g_timing.mu);
   for (auto &pr : g_timing.pending[which]) {
     float ms = 0.f;

@@ -1,0 +1,157 @@
+// masked.hip -- the single-operand scan: a float query against the ternary
+// database codes by masked addition (Sec. 5.1.2: the scalar product of a
+// ternary v with any w is the sum of w where v+ is set minus the sum of w
+// where v- is set; Sec. 6: comparing the ternary form with the original float
+// space is the more accurate variant).
+//
+// With the resident planes nz = v+ | v- and ng = v-, the score is
+//   sum_{nz} q_i - 2 sum_{ng} q_i.
+// Each workgroup first tabulates the query in LDS: for every group of four
+// coordinates g and every 4-bit mask m, lut[16 g + m] = the sum of the query
+// over the set bits of m, in double (exact: four floats).  A lane then scores
+// its tile vector with two table reads per nibble of its nz / ng words (all
+// lanes read the same group at the same time, so the 16 entries they can hit
+// are distinct), accumulating in double; the score is that sum rounded once
+// to float.  Summed in double, the score differs from the sum in any other
+// order by far less than a float rounding step, so results agree with a
+// sequential reference except where a sum falls within ~1e-12 of a float
+// rounding boundary.  The rest is the plain scan's: tiles of 64 vectors
+// spread over the grid, a register top-k list per wave, an LDS merge per
+// workgroup, and the per-query merge.  Keys order floats exactly: the score's
+// bit pattern is mapped to an unsigned value with the same order (zeros of
+// both signs map to one value) and takes the place of Delta + 2^31 in the
+// 64-bit key.
+#include "tq_batched.h"
+#include "tq_device.h"
+
+namespace tqi {
+namespace {
+
+constexpr int kMaskedWaves = 4;
+constexpr int kMaskedBlock = 64 * kMaskedWaves;
+
+// float -> int32 whose (value + 2^31) is the order-preserving key word
+__device__ __forceinline__ int32_t float_rank(float f) {
+  const uint32_t u = __float_as_uint(f + 0.0f);  // -0 + +0 = +0
+  const uint32_t k = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+  return static_cast<int32_t>(k - kScoreBias);
+}
+
+template <int NC, int R>
+__global__ __launch_bounds__(kMaskedBlock) void scan_masked_kernel(const uint4 *__restrict__ tiles, int64_t n,
+                                                                  int64_t ntiles, int d, const float *__restrict__ q,
+                                                                  int k, uint64_t *__restrict__ partial) {
+  constexpr int kGroups = 32 * NC;  // 4 NC words per plane, 8 nibbles per word
+  __shared__ double lut[kGroups * 16];
+  __shared__ uint64_t lds[2][kMaskedWaves * 64 * R];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t nwaves = static_cast<int64_t>(gridDim.x) * kMaskedWaves;
+
+  for (int e = threadIdx.x; e < kGroups * 16; e += kMaskedBlock) {
+    const int g = e >> 4, m = e & 15;
+    double s = 0.0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = 4 * g + b;
+      if ((m >> b) & 1) s += i < d ? static_cast<double>(q[i]) : 0.0;
+    }
+    lut[e] = s;
+  }
+  __syncthreads();
+
+  WaveList<R> list;
+  list.clear();
+  uint64_t thr = 0;
+  const int km1 = k - 1;
+
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * kMaskedWaves + wave; t < ntiles; t += nwaves) {
+    const uint4 *tile = tiles + t * (2 * NC * 64);
+    u32x4 vz[NC], vg[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      vz[c] = load_stream(tile + c * 64 + lane);
+      vg[c] = load_stream(tile + (NC + c) * 64 + lane);
+    }
+    double sp[2] = {0.0, 0.0}, sm[2] = {0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const uint32_t z = vz[c][w], g = vg[c][w];
+        const double *row = lut + (4 * c + w) * 8 * 16;
+#pragma unroll
+        for (int nib = 0; nib < 8; ++nib) {
+          sp[nib & 1] += row[nib * 16 + ((z >> (4 * nib)) & 15)];
+          sm[nib & 1] += row[nib * 16 + ((g >> (4 * nib)) & 15)];
+        }
+      }
+    }
+    const float score = static_cast<float>((sp[0] + sp[1]) - 2.0 * (sm[0] + sm[1]));
+    const int64_t id = t * 64 + lane;
+    const uint64_t key = make_key(float_rank(score), static_cast<uint32_t>(id));
+    offer_keys<R>(list, thr, key, id < n, km1, lane);
+  }
+
+  uint64_t *a = lds[0];
+  uint64_t *b = lds[1];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int p = r * 64 + lane;
+    if (p < k) a[wave * k + p] = list.v[r];
+  }
+  uint64_t *res = tree_merge(a, b, kMaskedWaves, k);
+  for (int p = threadIdx.x; p < k; p += kMaskedBlock) partial[static_cast<int64_t>(blockIdx.x) * k + p] = res[p];
+}
+
+// The merge writes key_score(key) = key word - 2^31 into the int32 scores;
+// turn those back into the floats they encode, in place.
+__global__ void rank_to_float_kernel(int32_t *__restrict__ scores, int64_t count) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const uint32_t k = static_cast<uint32_t>(scores[i]) + kScoreBias;
+  const uint32_t u = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+  scores[i] = static_cast<int32_t>(u);
+}
+
+template <int NC, int R>
+hipError_t launch_m(const DbDev &db, const float *q, int k, int grid, uint64_t *partial, hipStream_t s) {
+  hipLaunchKernelGGL((scan_masked_kernel<NC, R>), dim3(grid), dim3(kMaskedBlock), 0, s, db.tiles, db.n, db.ntiles,
+                     db.d, q, k, partial);
+  return hipGetLastError();
+}
+
+template <int NC>
+hipError_t launch_mr(const DbDev &db, const float *q, int k, int grid, uint64_t *partial, hipStream_t s) {
+  switch (rows_for_k(k)) {
+    case 1: return launch_m<NC, 1>(db, q, k, grid, partial, s);
+    case 2: return launch_m<NC, 2>(db, q, k, grid, partial, s);
+    case 4: return launch_m<NC, 4>(db, q, k, grid, partial, s);
+    default: return launch_m<NC, 8>(db, q, k, grid, partial, s);
+  }
+}
+
+}  // namespace
+
+hipError_t scan_masked_launch(const DbDev &db, const float *q, int k, int grid, uint64_t *partial, hipStream_t s) {
+  switch (db.nc) {
+    case 1: return launch_mr<1>(db, q, k, grid, partial, s);
+    case 2: return launch_mr<2>(db, q, k, grid, partial, s);
+    case 3: return launch_mr<3>(db, q, k, grid, partial, s);
+    case 4: return launch_mr<4>(db, q, k, grid, partial, s);
+    case 5: return launch_mr<5>(db, q, k, grid, partial, s);
+    case 6: return launch_mr<6>(db, q, k, grid, partial, s);
+    case 7: return launch_mr<7>(db, q, k, grid, partial, s);
+    case 8: return launch_mr<8>(db, q, k, grid, partial, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t rank_to_float_launch(int32_t *scores, int64_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(rank_to_float_kernel, dim3(static_cast<unsigned>((count + 255) / 256)), dim3(256), 0, s, scores,
+                     count);
+  return hipGetLastError();
+}
+
+}  // namespace tqi

@@ -45,4 +45,35 @@ int search_plain(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids,
   return TQ_OK;
 }
 
+// Masked addition of float queries (one database pass per query, like the
+// plain path); the merge's int32 scores are the order-preserving key words of
+// the float scores and are turned back into floats in place.
+int search_masked(tq_db *db, const float *Q, int nq, int k, int32_t *ids, float *scores, int grid, hipStream_t s) {
+  const int G = grid > 0 ? grid : default_plain_grid(db);
+  const size_t per_query = static_cast<size_t>(G) * k * sizeof(uint64_t);
+  const int chunk = static_cast<int>(std::max<size_t>(1, std::min<size_t>(nq, kPartialBudget / per_query)));
+  const size_t mid_keys = static_cast<size_t>(tqi::merge_mid_keys(chunk, G, k));
+  void *p = nullptr;
+  int rc = scratch_get(db->scratch, s, per_query * chunk + mid_keys * sizeof(uint64_t), &p);
+  if (rc) return rc;
+  uint64_t *partial = static_cast<uint64_t *>(p);
+  uint64_t *mid = partial + static_cast<size_t>(chunk) * G * k;
+  int32_t *iscores = reinterpret_cast<int32_t *>(scores);
+  for (int q0 = 0; q0 < nq; q0 += chunk) {
+    const int nc = std::min(chunk, nq - q0);
+    for (int i = 0; i < nc; ++i) {
+      TimedLaunch t(kTimeMasked, s);
+      hipError_t e = tqi::scan_masked_launch(db->dev, Q + static_cast<int64_t>(q0 + i) * db->dev.d, k, G,
+                                             partial + static_cast<size_t>(i) * G * k, s);
+      if (e != hipSuccess) return hip_fail(e, "masked scan launch");
+    }
+    hipError_t e = tqi::merge_launch(partial, nc, G, k, ids + static_cast<int64_t>(q0) * k,
+                                     iscores + static_cast<int64_t>(q0) * k, mid, s);
+    if (e == hipSuccess) e = tqi::rank_to_float_launch(iscores + static_cast<int64_t>(q0) * k,
+                                                       static_cast<int64_t>(nc) * k, s);
+    if (e != hipSuccess) return hip_fail(e, "masked merge launch");
+  }
+  return TQ_OK;
+}
+
 }  // namespace tqr

@@ -94,6 +94,13 @@ hipError_t merge_launch(const uint64_t *partial, int nq, int nlists, int k, int3
 hipError_t delta_dump_launch(const DbDev &db, const uint32_t *qcodes, int nq, int32_t *out,
                              hipStream_t s);
 
+// masked.hip: the masked-addition scan of one float query (d floats, device)
+// against the database, writing `grid` sorted lists of k keys like
+// scan_plain_launch; after merge_launch, rank_to_float_launch turns the int32
+// scores (order-preserving key words of the float scores) into floats.
+hipError_t scan_masked_launch(const DbDev &db, const float *q, int k, int grid, uint64_t *partial, hipStream_t s);
+hipError_t rank_to_float_launch(int32_t *scores, int64_t count, hipStream_t s);
+
 // rerank.hip: the k best of each query's ncand candidate rows of X (n x d
 // floats) by the double-precision scalar product with the query (nq x d).
 constexpr int kMaxRerank = 1024;  // candidates per query

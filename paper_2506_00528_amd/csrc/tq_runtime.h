@@ -42,7 +42,7 @@ class DeviceGuard {
 };
 
 // --- kernel timing ----------------------------------------------------------
-enum TimingFamily { kTimePlain = 0, kTimeBatched = 1 };
+enum TimingFamily { kTimePlain = 0, kTimeBatched = 1, kTimeMasked = 2, kTimeFamilies = 3 };
 
 bool timing_enabled();
 
@@ -94,6 +94,7 @@ namespace tqr {
 int default_plain_grid(const tq_db *db);
 int search_plain(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids, int32_t *scores, int grid,
                  hipStream_t s);
+int search_masked(tq_db *db, const float *Q, int nq, int k, int32_t *ids, float *scores, int grid, hipStream_t s);
 
 // batched.cpp
 int choose_path(tq_db *db, int requested, int nq, int k);

@@ -44,6 +44,7 @@ EXPORTS = (
     "tq_db_export", "tq_db_info", "tq_db_destroy", "tq_search_knn", "tq_autotune", "tq_delta_dump", "tq_sync",
     "tq_serve_create", "tq_serve_submit", "tq_serve_poll", "tq_serve_wait", "tq_serve_cancel",
     "tq_serve_stats", "tq_serve_destroy", "tq_timing_enable", "tq_timing_read", "tq_rerank",
+    "tq_search_masked",
 )
 
 
@@ -99,6 +100,7 @@ def lib(path: Optional[str] = None):
         "tq_autotune": ([vp, i32, P(i32), i32, vp], i32),
         "tq_delta_dump": ([vp, vp, i32, vp, vp], i32),
         "tq_rerank": ([vp, i64, i32, vp, i32, vp, i32, i32, vp, vp, vp], i32),
+        "tq_search_masked": ([vp, vp, i32, i32, vp, vp, P(tq_search_opts), vp], i32),
         "tq_sync": ([vp], i32),
         "tq_serve_create": ([vp, P(tq_serve_cfg), P(vp)], i32),
         "tq_serve_submit": ([vp, vp, i32, i32, P(u64)], i32),
@@ -282,6 +284,26 @@ def tq_delta_dump(db: tq_db, qcodes: torch.Tensor, stream=None) -> torch.Tensor:
         _check(lib().tq_delta_dump(db.handle, _dev(qcodes, "qcodes", torch.int32), nq,
                                    _dev(out, "delta", torch.int32), _stream(qcodes, stream)), "tq_delta_dump")
     return out
+
+
+def tq_search_masked(db: "tq_db", Q: torch.Tensor, k: int, grid: int = 0, ids: Optional[torch.Tensor] = None,
+                     scores: Optional[torch.Tensor] = None, stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """k nearest database codes of each float query by masked addition
+    (see tq.h); Q: nq x d float32 on the GPU."""
+    nq = int(Q.shape[0])
+    if Q.dim() != 2 or int(Q.shape[1]) != db.d:
+        raise ValueError("Q must be nq x d")
+    with torch.cuda.device(db.device):
+        if ids is None:
+            ids = torch.empty((nq, k), dtype=torch.int32, device=db.device)
+        if scores is None:
+            scores = torch.empty((nq, k), dtype=torch.float32, device=db.device)
+        opts = tq_search_opts()
+        opts.grid = int(grid)
+        _check(lib().tq_search_masked(db.handle, _dev(Q, "Q", torch.float32), nq, int(k),
+                                      _dev(ids, "ids", torch.int32), _dev(scores, "scores", torch.float32),
+                                      ctypes.byref(opts), _stream(Q, stream)), "tq_search_masked")
+    return ids, scores
 
 
 TQ_MAX_RERANK = 1024

@@ -362,9 +362,54 @@ def check_rerank_invariants(o, seed=13):
     assert np.all(ids3[:, 0] == 3) and np.all(ids3[:, 1:] == -1) and np.all(np.isneginf(sc3[:, 1:]))
 
 
+# ---------------------------------------------------------------------------
+# masked addition: float query against ternary vectors (Sec. 5.1.2, Sec. 6)
+# ---------------------------------------------------------------------------
+
+def check_masked_ternary_query_is_delta(o, seed=14):
+    """A ternary query (values -1, 0, +1 as floats) makes masked addition the
+    ternary scalar product, i.e. b2sp = Delta (Sec. 5.1.2 defines both as the
+    scalar product): same scores, and the same top-k order (ties: lower id)."""
+    rng = np.random.default_rng(seed)
+    d, x, n, k = 40, 15, 500, 30
+    V = o.encode(rng.standard_normal((n, d)).astype(np.float32), x)
+    VQ = o.encode(rng.standard_normal((4, d)).astype(np.float32), x)
+    ids, sc, ex = o.masked_knn(VQ.astype(np.float32), V, k)
+    kid, ksc = o.knn(VQ, V, k)
+    assert np.array_equal(ids, kid)
+    assert np.array_equal(sc, ksc.astype(np.float32)) and np.array_equal(ex, ksc.astype(np.float64))
+
+
+def check_masked_float_query(o, seed=15):
+    """For a float query the double sums equal the scalar product with the
+    ternary vector (computed here by a library product, in another order) to
+    well within double rounding; the float score is that sum rounded once;
+    results are ordered by float score, ties to the lower id, and nothing
+    left out beats the k-th."""
+    rng = np.random.default_rng(seed)
+    d, x, n, k = 100, 67, 800, 40
+    V = o.encode(rng.standard_normal((n, d)).astype(np.float32), x)
+    V[5] = V[9]  # equal vectors: equal scores, the lower id first
+    Q = rng.standard_normal((5, d)).astype(np.float32)
+    ids, sc, ex = o.masked_knn(Q, V, k)
+    full = Q.astype(np.float64) @ V.astype(np.float64).T
+    for q in range(5):
+        bound = 1e-12 * float(np.abs(Q[q]).sum())
+        assert np.all(np.abs(ex[q] - full[q, ids[q]]) <= bound)
+        assert np.array_equal(sc[q], ex[q].astype(np.float32))
+        for j in range(1, k):
+            assert sc[q, j - 1] > sc[q, j] or (sc[q, j - 1] == sc[q, j] and ids[q, j - 1] < ids[q, j])
+        rest = np.setdiff1d(np.arange(n), ids[q])
+        f32 = full[q, rest].astype(np.float32)
+        assert np.all((f32 < sc[q, -1]) | ((f32 == sc[q, -1]) & (rest > ids[q, -1])))
+        if 5 in ids[q] and 9 in ids[q]:
+            assert list(ids[q]).index(5) < list(ids[q]).index(9)
+
+
 ALL_CHECKS = [
     check_table3_encode, check_enumeration_argmax, check_fig2_cuboctahedron, check_special_cases,
     check_invariants, check_ties_and_zeros, check_table3_pack, check_pack_layout, check_table3_delta,
     check_delta_identities, check_delta_one_bit_hamming, check_delta_bitwise, check_knn_bruteforce,
     check_knn_ties, check_knn_shard_merge, check_rerank_l2_order, check_rerank_invariants,
+    check_masked_ternary_query_is_delta, check_masked_float_query,
 ]

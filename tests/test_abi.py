@@ -81,3 +81,10 @@ def test_rerank_host_validation_without_gpu(tq):
     assert "k=5" in tq.last_error()
     assert L.tq_rerank(p, 10, 8, p, 1, p, 4, 0, p, p, None) == tq.TQ_ERR_INVALID
     assert L.tq_rerank(p, 10, 8, p, 0, p, 4, 2, p, p, None) == tq.TQ_OK  # nothing to do
+
+
+def test_masked_host_validation_without_gpu(tq):
+    L = tq.lib()
+    p = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
+    assert L.tq_search_masked(None, p, 1, 1, p, p, None, None) == tq.TQ_ERR_INVALID
+    assert L.tq_timing_read(3, None, None, 0) == tq.TQ_ERR_INVALID

@@ -1,0 +1,139 @@
+"""Masked-addition search of float queries (tq_search_masked) against the
+oracle's.  Both sum in double and round once to float; the sums are taken in
+different orders, so a float score may differ by one unit in the last place
+where the double sum lies within ~1e-12 of a rounding boundary.  Where every
+score of a query matches (the normal case) the ids must match exactly; a
+query with such a boundary case is checked by properties instead (every
+returned score is the rounded scalar product of its id, the order is (score
+desc, id asc), and nothing left out beats the k-th)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from tests.libtq import ensure_built
+from workloads import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stderr.flush()
+
+
+@pytest.fixture(scope="module")
+def tq():
+    return ensure_built()
+
+
+@pytest.fixture(scope="module")
+def o():
+    return oracle.default()
+
+
+def dev_codes(c):
+    return torch.from_numpy(np.ascontiguousarray(c).view(np.int32).copy()).cuda()
+
+
+def check(gi, gs, ei, es, Q, V, exact_required=False):
+    full = None
+    for q in range(ei.shape[0]):
+        if np.array_equal(gs[q], es[q]):
+            assert np.array_equal(gi[q], ei[q]), q
+            continue
+        assert not exact_required, f"query {q}: scores differ"
+        if full is None:
+            full = Q.astype(np.float64) @ V.astype(np.float64).T
+        row = full[q]
+        k = gi.shape[1]
+        assert len(set(gi[q].tolist())) == k
+        for j in range(k):
+            f = np.float32(row[gi[q, j]])
+            assert abs(float(gs[q, j]) - float(f)) <= float(np.spacing(np.float32(abs(f)))), (q, j)
+            if j:
+                assert gs[q, j - 1] > gs[q, j] or (gs[q, j - 1] == gs[q, j] and gi[q, j - 1] < gi[q, j])
+        rest = np.setdiff1d(np.arange(V.shape[0]), gi[q])
+        lim = float(gs[q, -1]) + float(np.spacing(np.float32(abs(gs[q, -1]))))
+        assert np.all(row[rest].astype(np.float32) <= lim), q
+
+
+def run(tq, db, Q, k, **kw):
+    ids, sc = tq.tq_search_masked(db, torch.from_numpy(np.ascontiguousarray(Q, dtype=np.float32)).cuda(), k, **kw)
+    torch.cuda.synchronize()
+    return ids.cpu().numpy(), sc.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def small(tq, o):
+    w = datagen.WORKLOADS["small"]
+    X = datagen.rows("small", datagen.DB, 0, w["n"]).numpy()
+    Q = datagen.rows("small", datagen.QUERIES, 0, 40).numpy()
+    V = o.encode(X, w["x"])
+    db = tq.tq_db_create(dev_codes(o.pack(V)), w["d"], w["x"])
+    yield dict(V=V, Q=Q, db=db)
+    db.destroy()
+
+
+@pytest.mark.parametrize("k", [1, 10, 64, 65, 100, 257, 512])
+def test_masked_small_workload(tq, o, small, k):
+    say(f"masked small workload k={k}")
+    gi, gs = run(tq, small["db"], small["Q"], k)
+    ei, es, _ = o.masked_knn(small["Q"], small["V"], k)
+    check(gi, gs, ei, es, small["Q"], small["V"])
+
+
+@pytest.mark.parametrize("grid", [1, 3, 40, 512])
+def test_masked_grids(tq, o, small, grid):
+    say(f"masked small workload grid={grid}")
+    gi, gs = run(tq, small["db"], small["Q"][:7], 10, grid=grid)
+    ei, es, _ = o.masked_knn(small["Q"][:7], small["V"], 10)
+    check(gi, gs, ei, es, small["Q"][:7], small["V"])
+
+
+@pytest.mark.parametrize("d", [1, 31, 33, 64, 100, 129, 384, 500, 768, 1000, 1024])
+def test_masked_dims(tq, o, d):
+    rng = np.random.default_rng(400 + d)
+    n, x = 2500, max(1, (2 * d) // 3)
+    V = o.encode(rng.standard_normal((n, d)).astype(np.float32), x)
+    Q = rng.standard_normal((6, d)).astype(np.float32)
+    Q[1] *= 1e-20  # tiny and huge magnitudes
+    Q[2] *= 1e20
+    db = tq.tq_db_create(dev_codes(o.pack(V)), d, x)
+    say(f"masked d={d} n={n} x={x}")
+    for k in (1, 17, 100):
+        gi, gs = run(tq, db, Q, k)
+        ei, es, _ = o.masked_knn(Q, V, k)
+        check(gi, gs, ei, es, Q, V)
+    db.destroy()
+
+
+def test_masked_ternary_queries_are_exact(tq, o):
+    """Ternary-valued float queries give integer scores (= Delta): exact, with
+    many ties, which must go to the lower id."""
+    rng = np.random.default_rng(31)
+    d, x = 256, 64
+    base = o.encode(rng.standard_normal((8, d)).astype(np.float32), x)
+    V = base[rng.integers(0, 8, size=9000)]
+    VQ = np.concatenate([base[:2], o.encode(rng.standard_normal((10, d)).astype(np.float32), x)])
+    db = tq.tq_db_create(dev_codes(o.pack(V)), d, x)
+    say("masked ternary queries, heavy ties")
+    for k in (1, 10, 100, 512):
+        gi, gs = run(tq, db, VQ.astype(np.float32), k)
+        ei, es, _ = o.masked_knn(VQ.astype(np.float32), V, k)
+        check(gi, gs, ei, es, VQ.astype(np.float32), V, exact_required=True)
+        kid, ksc = o.knn(VQ, V, k)  # and they are the Delta search's results
+        assert np.array_equal(gi, kid) and np.array_equal(gs, ksc.astype(np.float32))
+    db.destroy()
+
+
+def test_masked_rejects(tq, small):
+    Q = torch.zeros((2, 384), dtype=torch.float32, device="cuda")
+    with pytest.raises(tq.TQError):
+        tq.tq_search_masked(small["db"], Q, 0)
+    with pytest.raises(tq.TQError):
+        tq.tq_search_masked(small["db"], Q, 513)
+    with pytest.raises(ValueError):
+        tq.tq_search_masked(small["db"], torch.zeros((2, 100), dtype=torch.float32, device="cuda"), 5)

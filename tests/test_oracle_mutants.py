@@ -17,6 +17,7 @@ MUTANTS = {
     5: "bit planes packed most-significant-bit first",
     6: "rerank keeps the worst candidates",
     7: "rerank ties go to the higher id",
+    8: "masked addition ignores the sign",
 }
 
 
