@@ -89,6 +89,14 @@ int tq_version(void);
  * TQ_ERR_INVALID if d < 1 or d > TQ_MAX_D. */
 int tq_code_words(int d);
 
+/* The x in 1..d with the most {x,d} vertices, C(d,x) * 2^x (Sec. 5.1.1: the
+ * construction that maximises the number of Voronoi cells; Sec. 2.3 for the
+ * count).  The count grows while 2(d - x) >= x + 1, so the maximum is at
+ * ceil((2d - 1) / 3); when 3 divides 2d - 1 two neighbours tie and the
+ * smaller is returned (which reproduces the paper's {333, 500}).  Returns
+ * TQ_ERR_INVALID if d < 1 or d > TQ_MAX_D. */
+int tq_default_x(int d);
+
 /* ---------------------------------------------------------------------- */
 /* Encode (Sec. 2.4, nearest {x,d} EVP vertex; Sec. 5.1.2 bit planes)      */
 /* ---------------------------------------------------------------------- */

@@ -221,6 +221,11 @@ int tq_code_words(int d) {
   return (d + 31) / 32;
 }
 
+int tq_default_x(int d) {
+  if (d < 1 || d > TQ_MAX_D) return fail(TQ_ERR_INVALID, "d=%d outside [1, %d]", d, TQ_MAX_D);
+  return (2 * d + 1) / 3;  // ceil((2d - 1) / 3)
+}
+
 int tq_encode(const float *X, int64_t n, int d, int x, uint32_t *codes, void *stream) {
   clear_error();
   if (n < 0) return fail(TQ_ERR_INVALID, "n=%lld < 0", (long long)n);

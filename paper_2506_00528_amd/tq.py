@@ -44,7 +44,7 @@ EXPORTS = (
     "tq_db_export", "tq_db_info", "tq_db_destroy", "tq_search_knn", "tq_autotune", "tq_delta_dump", "tq_sync",
     "tq_serve_create", "tq_serve_submit", "tq_serve_poll", "tq_serve_wait", "tq_serve_cancel",
     "tq_serve_stats", "tq_serve_destroy", "tq_timing_enable", "tq_timing_read", "tq_rerank",
-    "tq_search_masked",
+    "tq_search_masked", "tq_default_x",
 )
 
 
@@ -91,6 +91,7 @@ def lib(path: Optional[str] = None):
         "tq_last_error": ([], ctypes.c_char_p),
         "tq_version": ([], i32),
         "tq_code_words": ([i32], i32),
+        "tq_default_x": ([i32], i32),
         "tq_encode": ([vp, i64, i32, i32, vp, vp], i32),
         "tq_db_create": ([vp, i64, i32, i32, vp, P(vp)], i32),
         "tq_db_export": ([vp, vp, vp], i32),
@@ -150,6 +151,14 @@ def _dev(t: torch.Tensor, name: str, dtype: torch.dtype) -> int:
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     return t.data_ptr()
+
+
+def tq_default_x(d: int) -> int:
+    """x with the most {x,d} vertices (see tq.h)."""
+    r = lib().tq_default_x(int(d))
+    if r < 0:
+        _check(r, "tq_default_x")
+    return r
 
 
 def tq_code_words(d: int) -> int:

@@ -88,3 +88,14 @@ def test_masked_host_validation_without_gpu(tq):
     p = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
     assert L.tq_search_masked(None, p, 1, 1, p, p, None, None) == tq.TQ_ERR_INVALID
     assert L.tq_timing_read(3, None, None, 0) == tq.TQ_ERR_INVALID
+
+
+def test_default_x_against_the_oracle(tq):
+    """The library's closed form against the oracle's brute force over exact
+    big-integer vertex counts, for every supported d."""
+    import oracle
+    for d in range(1, tq.TQ_MAX_D + 1):
+        assert tq.tq_default_x(d) == oracle.default_x(d), d
+    for bad in (0, -1, tq.TQ_MAX_D + 1):
+        with pytest.raises(tq.TQError):
+            tq.tq_default_x(bad)
