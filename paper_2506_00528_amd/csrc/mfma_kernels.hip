@@ -77,15 +77,16 @@ struct TileStage {
   static constexpr int kPer = (NC + 3) / 4;
   uint4 nz[kPer], ng[kPer];
 
+  // Every thread issues the same loads (a chunk past NC re-reads chunk
+  // NC - 1 and is not stored), so no branch separates the loads of one tile
+  // from the next and two tiles can stay in flight.
   __device__ __forceinline__ void load(const uint4 *__restrict__ tiles, int64_t t, int j) {
     const int v = j & 63, s0 = j >> 6;
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
-      const int s = s0 + 4 * i;
-      if (s < NC) {
-        nz[i] = tiles[((t * 2 + 0) * NC + s) * 64 + v];
-        ng[i] = tiles[((t * 2 + 1) * NC + s) * 64 + v];
-      }
+      const int s = min(s0 + 4 * i, NC - 1);
+      nz[i] = tiles[((t * 2 + 0) * NC + s) * 64 + v];
+      ng[i] = tiles[((t * 2 + 1) * NC + s) * 64 + v];
     }
   }
   // operand (s, cb) of lane l lives at op[(s * 4 + cb) * 64 + l]
