@@ -118,6 +118,15 @@ int tq_default_x(int d);
  * tq_sync() reports as TQ_ERR_INVALID. */
 int tq_encode(const float *X, int64_t n, int d, int x, uint32_t *codes, void *stream);
 
+/* The b1.58 quantisation the paper compares against (Sec. 4.3), applied per
+ * embedding: gamma = mean |u_i| of the row, v_i = max(-1, min(1, round(u_i /
+ * gamma))) with round-half-to-even, in double precision (gamma summed in
+ * double); an all-zero row gives the zero vector.  Same layout, limits and
+ * NaN / infinity handling as tq_encode.  The number of non-zeros varies from
+ * row to row, so such codes form a database with x = 0 (tq_db_create), where
+ * Delta is the plain ternary scalar product. */
+int tq_encode_b158(const float *X, int64_t n, int d, uint32_t *codes, void *stream);
+
 /* ---------------------------------------------------------------------- */
 /* Database (the pre-processed set S of Sec. 1.1)                          */
 /* ---------------------------------------------------------------------- */
@@ -127,11 +136,14 @@ typedef struct tq_db tq_db;
 /* Build a resident database from n canonical codes of an {x,d} EVP.
  *
  *   codes  device pointer, n x 2W uint32, canonical layout.
+ *   x      the codes' number of non-zeros, or 0 for ternary codes with any
+ *          number of them (e.g. tq_encode_b158).
  *
  * The library copies the codes into its own device memory (re-tiled for
  * streaming; the bits are unchanged) and checks every row: exactly x
- * non-zeros, no coordinate in both planes, zero padding bits.  A malformed
- * row gives TQ_ERR_INVALID and no database.  Requires 1 <= n < 2^31.  The
+ * non-zeros (any number when x = 0), no coordinate in both planes, zero
+ * padding bits.  A malformed row gives TQ_ERR_INVALID and no database.
+ * Requires 1 <= n < 2^31, 0 <= x <= d.  The
  * call waits for its GPU work on `stream`, so `codes` may be freed when it
  * returns.  *out is owned by the caller; release it with tq_db_destroy().
  * A database is read-only after creation: any number of searches may use it

@@ -8,7 +8,8 @@ The arithmetic lives in ``oracle.c`` (plain C + OpenMP, built with gcc); this
 module only marshals numpy arrays (encode, pack, unpack, delta, knn, the
 refinement of proxy candidates with the float vectors, rerank, and the
 masked-addition search of float queries against ternary vectors,
-masked_knn), plus a few pure-Python definitions:
+masked_knn, and the b1.58 quantisation of Sec. 4.3, encode_b158), plus a few
+pure-Python definitions:
 
 * ``default_x(d)``     -- the x maximising the vertex count C(d,x)*2^x
                           (Sec. 5.1.1), by brute force over all x with exact
@@ -57,6 +58,7 @@ def load(path: str | None = None):
     lib.oracle_knn.argtypes = [vp, i64, vp, i64, i32, i32, vp, vp]
     lib.oracle_rerank.argtypes = [vp, i64, i32, vp, i64, vp, i32, i32, vp, vp]
     lib.oracle_masked_knn.argtypes = [vp, i64, vp, i64, i32, i32, vp, vp, vp]
+    lib.oracle_encode_b158.argtypes = [vp, i64, i32, vp]
     lib.oracle_num_threads.restype = i32
     lib.oracle_set_num_threads.argtypes = [i32]
     if path is None:
@@ -91,6 +93,18 @@ class Oracle:
         rc = self.lib.oracle_encode(X.ctypes.data, n, d, int(x), V.ctypes.data)
         if rc != 0:
             raise OracleError(rc, "encode")
+        return V
+
+    # -- b1.58 quantisation (Sec. 4.3), per embedding --------------------
+    def encode_b158(self, X: np.ndarray) -> np.ndarray:
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        if X.ndim == 1:
+            X = X[None, :]
+        n, d = X.shape
+        V = np.empty((n, d), dtype=np.int8)
+        rc = self.lib.oracle_encode_b158(X.ctypes.data, n, d, V.ctypes.data)
+        if rc != 0:
+            raise OracleError(rc, "encode_b158")
         return V
 
     # -- bit planes (Sec. 5.1.2, Table 3) ---------------------------------
@@ -255,3 +269,7 @@ def rerank(X, Q, cand, k):
 
 def masked_knn(Q, V, k):
     return default().masked_knn(Q, V, k)
+
+
+def encode_b158(X):
+    return default().encode_b158(X)

@@ -27,6 +27,8 @@
  *            Sec. 5.3 measures), the first k kept.
  *   masked : exhaustive kNN of a float query against the ternary vectors by
  *            masked addition (Sec. 5.1.2; the asymmetric variant of Sec. 6).
+ *   b1.58  : the absmean ternary quantisation the paper compares against
+ *            (Sec. 4.3), per embedding.
  *
  * Readings taken where the paper is silent (each is listed in the design notes):
  *   - equal magnitudes at the x-th place: the lower coordinate index wins;
@@ -466,4 +468,52 @@ int oracle_masked_knn(const float *Q, int64_t nq, const int8_t *V, int64_t n, in
   free(all);
   free(tmp);
   return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* b1.58 quantisation (Sec. 4.3), one embedding at a time                   */
+/* ------------------------------------------------------------------------ */
+/*
+ * gamma = the mean of |u_i| over the vector (the paper's mean over a weight
+ * matrix, taken per embedding here), then v_i = max(-1, min(1, round(u_i /
+ * gamma))).  gamma is summed in double in index order, the division is in
+ * double, and round() is to nearest with ties to even (the IEEE default; the
+ * paper does not say).  The paper's epsilon only keeps an all-zero matrix
+ * from dividing by zero: an all-zero row gives the zero vector here.
+ */
+int oracle_encode_b158(const float *X, int64_t n, int d, int8_t *V) {
+  if (n < 0 || d < 1) return ORACLE_EINVAL;
+  int rc = 0;
+#pragma omp parallel for schedule(static) reduction(min : rc)
+  for (int64_t r = 0; r < n; ++r) {
+    const float *u = X + r * (int64_t)d;
+    int8_t *v = V + r * (int64_t)d;
+    double gamma = 0.0;
+    int finite = 1;
+    for (int i = 0; i < d; ++i) {
+      if (!isfinite(u[i])) finite = 0;
+      gamma += fabs((double)u[i]);
+    }
+    if (!finite) {
+      rc = ORACLE_ENONFINITE;
+      memset(v, 0, (size_t)d);
+      continue;
+    }
+    gamma /= (double)d;
+    for (int i = 0; i < d; ++i) {
+      if (gamma == 0.0) {
+        v[i] = 0;
+        continue;
+      }
+#if ORACLE_MUTANT == 9
+      double q = round((double)u[i] / gamma); /* planted: ties away from zero */
+#else
+      double q = nearbyint((double)u[i] / gamma);
+#endif
+      if (q > 1.0) q = 1.0;
+      if (q < -1.0) q = -1.0;
+      v[i] = (int8_t)q;
+    }
+  }
+  return rc;
 }

@@ -243,6 +243,22 @@ int tq_encode(const float *X, int64_t n, int d, int x, uint32_t *codes, void *st
   return TQ_OK;
 }
 
+int tq_encode_b158(const float *X, int64_t n, int d, uint32_t *codes, void *stream) {
+  clear_error();
+  if (n < 0) return fail(TQ_ERR_INVALID, "n=%lld < 0", (long long)n);
+  if (d < 1 || d > TQ_MAX_D) return fail(TQ_ERR_INVALID, "d=%d outside [1, %d]", d, TQ_MAX_D);
+  if (n == 0) return TQ_OK;
+  if (!X || !codes) return fail(TQ_ERR_INVALID, "null X or codes");
+  int dev;
+  int rc = current_device(&dev);
+  if (rc) return rc;
+  DevCtx *ctx;
+  if ((rc = device_ctx(dev, &ctx))) return rc;
+  hipError_t e = tqi::b158_launch(X, n, d, codes, ctx->flags, ctx->num_cu, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "b1.58 encode launch");
+  return TQ_OK;
+}
+
 int tq_sync(void *stream) {
   clear_error();
   int dev;
@@ -272,7 +288,7 @@ int tq_db_create(const uint32_t *codes, int64_t n, int d, int x, void *stream, t
   if (!codes) return fail(TQ_ERR_INVALID, "null codes");
   if (n < 1 || n > INT32_MAX) return fail(TQ_ERR_INVALID, "n=%lld outside [1, 2^31)", (long long)n);
   if (d < 1 || d > TQ_MAX_D) return fail(TQ_ERR_INVALID, "d=%d outside [1, %d]", d, TQ_MAX_D);
-  if (x < 1 || x > d) return fail(TQ_ERR_INVALID, "x=%d outside [1, d=%d]", x, d);
+  if (x < 0 || x > d) return fail(TQ_ERR_INVALID, "x=%d outside [0, d=%d]", x, d);
   int dev;
   int rc = current_device(&dev);
   if (rc) return rc;

@@ -224,6 +224,63 @@ __global__ __launch_bounds__(kEncodeBlock) void encode_kernel(const float *__res
   }
 }
 
+// b1.58 quantisation (Sec. 4.3), per embedding: gamma = mean |u_i|, then
+// v_i = clip(round(u_i / gamma), -1, 1) with ties to even, so v_i != 0 exactly
+// when |u_i / gamma| > 1/2.  gamma is summed in double (each lane its
+// coordinates in order, then a fixed shuffle tree; a sequential sum can
+// differ in the last bit, which moves a decision only for a quotient within
+// ~1e-16 of 1/2) and the quotient is formed in double; an all-zero row gives
+// the zero vector.  One wave per row,
+// packed with the same ballots as the EVP encoder.
+template <int J, int JV>
+__global__ __launch_bounds__(kEncodeBlock) void b158_kernel(const float *__restrict__ X, int64_t n, int d, int W,
+                                                           uint32_t *__restrict__ codes, int *__restrict__ flags) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves_per_block = kEncodeBlock / 64;
+  const int64_t nwaves = static_cast<int64_t>(gridDim.x) * waves_per_block;
+  const int row_words = 2 * W;
+  for (int64_t row = static_cast<int64_t>(blockIdx.x) * waves_per_block + (threadIdx.x >> 6); row < n;
+       row += nwaves) {
+    const float *u = X + row * d + lane;
+    float v[J];
+    uint32_t top = 0;
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      if (j < JV) v[j] = __builtin_nontemporal_load(u + 64 * j);
+      else v[j] = j * 64 + lane < d ? __builtin_nontemporal_load(u + 64 * j) : 0.0f;
+      top = max(top, __float_as_uint(v[j]) & 0x7FFFFFFFu);
+      s += fabs(static_cast<double>(v[j]));
+    }
+    uint32_t plus = 0, minus = 0;
+    if (__any(top >= kInfBits)) {
+      if (lane == 0) atomicOr(flags, 1);
+    } else {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+      const double gamma = s / static_cast<double>(d);
+      // round(q) is non-zero exactly when |q| > 1/2 (a tie rounds to even 0);
+      // q is the correctly rounded double quotient, as in a plain reference
+      constexpr auto js = std::make_integer_sequence<int, J>{};
+      pack_planes<J>(v, [&](int j) { return vote(gamma > 0.0 && fabs(static_cast<double>(v[j]) / gamma) > 0.5); },
+                     &plus, &minus, js);
+    }
+    const uint32_t mw = __shfl(minus, lane - W);
+    if (lane < row_words) codes[row * row_words + lane] = lane < W ? plus : mw;
+  }
+}
+
+template <int J, int JV>
+hipError_t launch_b(const float *X, int64_t n, int d, uint32_t *codes, int *flags, int num_cu, hipStream_t s) {
+  int64_t blocks = (n + 3) / 4;
+  const int64_t cap = static_cast<int64_t>(num_cu > 0 ? num_cu : 256) * 8;
+  if (blocks > cap) blocks = cap;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL((b158_kernel<J, JV>), dim3(static_cast<unsigned>(blocks)), dim3(kEncodeBlock), 0, s, X, n, d,
+                     (d + 31) / 32, codes, flags);
+  return hipGetLastError();
+}
+
 template <int J, int JV>
 hipError_t launch_j(const float *X, int64_t n, int d, int x, uint32_t *codes, int *flags, int num_cu,
                     hipStream_t s) {
@@ -249,6 +306,18 @@ hipError_t encode_launch(const float *X, int64_t n, int d, int x, uint32_t *code
   if (j <= 8) return launch_j<8, 6>(X, n, d, x, codes, flags, num_cu, s);
   if (j <= 12) return launch_j<12, 8>(X, n, d, x, codes, flags, num_cu, s);
   return launch_j<16, 12>(X, n, d, x, codes, flags, num_cu, s);
+}
+
+hipError_t b158_launch(const float *X, int64_t n, int d, uint32_t *codes, int *flags, int num_cu, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int j = (d + 63) / 64;
+  if (j <= 1) return launch_b<1, 0>(X, n, d, codes, flags, num_cu, s);
+  if (j <= 2) return launch_b<2, 1>(X, n, d, codes, flags, num_cu, s);
+  if (j <= 4) return launch_b<4, 2>(X, n, d, codes, flags, num_cu, s);
+  if (j <= 6) return launch_b<6, 4>(X, n, d, codes, flags, num_cu, s);
+  if (j <= 8) return launch_b<8, 6>(X, n, d, codes, flags, num_cu, s);
+  if (j <= 12) return launch_b<12, 8>(X, n, d, codes, flags, num_cu, s);
+  return launch_b<16, 12>(X, n, d, codes, flags, num_cu, s);
 }
 
 }  // namespace tqi

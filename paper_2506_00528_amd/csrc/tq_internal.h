@@ -73,6 +73,9 @@ inline int rows_for_k(int k) {
 hipError_t encode_launch(const float *X, int64_t n, int d, int x, uint32_t *codes, int *flags,
                          int num_cu, hipStream_t s);
 
+// b1.58 quantisation of each row (Sec. 4.3), same code layout and flags.
+hipError_t b158_launch(const float *X, int64_t n, int d, uint32_t *codes, int *flags, int num_cu, hipStream_t s);
+
 // layout.hip
 hipError_t repack_launch(const uint32_t *codes, int64_t n, int d, uint4 *tiles, int64_t ntiles,
                          int nc, hipStream_t s);

@@ -44,7 +44,7 @@ EXPORTS = (
     "tq_db_export", "tq_db_info", "tq_db_destroy", "tq_search_knn", "tq_autotune", "tq_delta_dump", "tq_sync",
     "tq_serve_create", "tq_serve_submit", "tq_serve_poll", "tq_serve_wait", "tq_serve_cancel",
     "tq_serve_stats", "tq_serve_destroy", "tq_timing_enable", "tq_timing_read", "tq_rerank",
-    "tq_search_masked", "tq_default_x",
+    "tq_search_masked", "tq_default_x", "tq_encode_b158",
 )
 
 
@@ -93,6 +93,7 @@ def lib(path: Optional[str] = None):
         "tq_code_words": ([i32], i32),
         "tq_default_x": ([i32], i32),
         "tq_encode": ([vp, i64, i32, i32, vp, vp], i32),
+        "tq_encode_b158": ([vp, i64, i32, vp, vp], i32),
         "tq_db_create": ([vp, i64, i32, i32, vp, P(vp)], i32),
         "tq_db_export": ([vp, vp, vp], i32),
         "tq_db_info": ([vp, P(i64), P(i32), P(i32), P(sz)], i32),
@@ -182,6 +183,22 @@ def tq_encode(X: torch.Tensor, x: int, codes: Optional[torch.Tensor] = None, str
             raise ValueError("codes has the wrong shape")
         _check(lib().tq_encode(_dev(X, "X", torch.float32), n, d, int(x), _dev(codes, "codes", torch.int32),
                                _stream(X, stream)), "tq_encode")
+    return codes
+
+
+def tq_encode_b158(X: torch.Tensor, codes: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """b1.58 (absmean) ternary codes of the rows of X (see tq.h)."""
+    if X.dim() != 2:
+        raise ValueError("X must be n x d")
+    n, d = X.shape
+    W = tq_code_words(d)
+    with torch.cuda.device(X.device):
+        if codes is None:
+            codes = torch.empty((n, 2 * W), dtype=torch.int32, device=X.device)
+        if tuple(codes.shape) != (n, 2 * W):
+            raise ValueError("codes has the wrong shape")
+        _check(lib().tq_encode_b158(_dev(X, "X", torch.float32), n, d, _dev(codes, "codes", torch.int32),
+                                    _stream(X, stream)), "tq_encode_b158")
     return codes
 
 

@@ -406,10 +406,39 @@ def check_masked_float_query(o, seed=15):
             assert list(ids[q]).index(5) < list(ids[q]).index(9)
 
 
+# ---------------------------------------------------------------------------
+# b1.58 quantisation (Sec. 4.3), per embedding
+# ---------------------------------------------------------------------------
+
+def check_b158_worked(o):
+    """Hand-worked rows: mean |u| = gamma, round(u / gamma) clipped to +-1,
+    ties to even, an all-zero row stays zero."""
+    X = np.array([[0.2, -0.5, 1.3, 0.0],    # gamma 0.5: 0.4, -1, 2.6, 0 -> 0, -1, 1, 0
+                  [1.0, 3.0, -1.0, -3.0],   # gamma 2: 0.5, 1.5, -0.5, -1.5 -> 0, 1, 0, -1
+                  [0.0, 0.0, 0.0, 0.0],
+                  [2.0, -2.0, 2.0, -2.0]],  # gamma 2: the sign vector
+                 dtype=np.float32)
+    V = o.encode_b158(X)
+    assert V.tolist() == [[0, -1, 1, 0], [0, 1, 0, -1], [0, 0, 0, 0], [1, -1, 1, -1]]
+
+
+def check_b158_properties(o, seed=16):
+    """Signs agree with u; scaling a row by a power of two changes nothing;
+    the non-zeros are exactly the coordinates with |u| above gamma / 2."""
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((200, 77)).astype(np.float32)
+    V = o.encode_b158(X)
+    assert np.all((V == 0) | (np.sign(V) == np.sign(X)))
+    assert np.array_equal(o.encode_b158(X * np.float32(8.0)), V)
+    assert np.array_equal(o.encode_b158(X * np.float32(2.0 ** -20)), V)
+    gamma = np.abs(X.astype(np.float64)).mean(1, keepdims=True)
+    assert np.array_equal(V != 0, np.abs(X.astype(np.float64)) / gamma > 0.5)
+
+
 ALL_CHECKS = [
     check_table3_encode, check_enumeration_argmax, check_fig2_cuboctahedron, check_special_cases,
     check_invariants, check_ties_and_zeros, check_table3_pack, check_pack_layout, check_table3_delta,
     check_delta_identities, check_delta_one_bit_hamming, check_delta_bitwise, check_knn_bruteforce,
     check_knn_ties, check_knn_shard_merge, check_rerank_l2_order, check_rerank_invariants,
-    check_masked_ternary_query_is_delta, check_masked_float_query,
+    check_masked_ternary_query_is_delta, check_masked_float_query, check_b158_worked, check_b158_properties,
 ]

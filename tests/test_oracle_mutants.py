@@ -18,6 +18,7 @@ MUTANTS = {
     6: "rerank keeps the worst candidates",
     7: "rerank ties go to the higher id",
     8: "masked addition ignores the sign",
+    9: "b1.58 rounds ties away from zero",
 }
 
 
