@@ -51,6 +51,9 @@ def parse():
     p.add_argument("--rerank", type=int, default=512,
                    help="refine the top-N Delta candidates of the recall queries with the float vectors "
                         "(keeps the float database resident on the GPU); 0 = off")
+    p.add_argument("--sparse-x", type=int, default=-1,
+                   help="x of a second database (same vectors) scanned with the index-list engine; "
+                        "-1 = d/32, 0 = off")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-rows", type=int, default=1 << 20)
     p.add_argument("--cpu-sample-queries", type=int, default=160)
@@ -173,6 +176,8 @@ def run_serving(tq, torch, args, log):
     codes = torch.empty((n, 2 * W), dtype=torch.int32, device=dev)
     for r0, X in datagen.iter_rows(wl["spec"], datagen.DB, 0, n, dev):
         tq.tq_encode(X, x, codes[r0:r0 + X.shape[0]])
+        if sp_codes is not None:
+            tq.tq_encode(X, xs, sp_codes[r0:r0 + X.shape[0]])
         gt.add(X, r0)
     tq.tq_sync()
     db = tq.tq_db_create(codes, d, x)
@@ -292,10 +297,15 @@ def main():
     nrec = min(args.recall_queries, nq_total)
     gt = metrics.ExactTopK(queries[:nrec], 10)
     codes = torch.empty((n, 2 * W), dtype=torch.int32, device=dev)
+    # the same vectors at a small x, for the index-list engine (kept when 8x <= d)
+    xs = d // 32 if args.sparse_x < 0 else args.sparse_x
+    sp_codes = torch.empty((n, 2 * W), dtype=torch.int32, device=dev) if 0 < xs and 8 * xs <= d else None
     cpu_rows = min(args.cpu_sample_rows, n) if not args.no_cpu_baseline else 0
     cpu_X = np.empty((cpu_rows, d), dtype=np.float32) if cpu_rows else None
     for r0, X in datagen.iter_rows(spec, datagen.DB, 0, n, dev):
         tq.tq_encode(X, x, codes[r0:r0 + X.shape[0]])
+        if sp_codes is not None:
+            tq.tq_encode(X, xs, sp_codes[r0:r0 + X.shape[0]])
         gt.add(X, r0)
         if cpu_rows and r0 < cpu_rows:
             m = min(X.shape[0], cpu_rows - r0)
@@ -351,6 +361,50 @@ def main():
                            "avg_launch_ms": round(m_avg, 4), "launches": m_launches}}
     log(f"masked addition: recall@10 {masked['recall_at_10']}, {m_avg:.3f} ms per query scan "
         f"({masked['roofline']['frac'] * 100:.1f}% of HBM)")
+
+    # ---- index-list engine on the small-x database: recall, QPS and HBM rate
+    sparse = None
+    if sp_codes is not None:
+        sdb = tq.tq_db_create(sp_codes, d, xs)
+        del sp_codes
+        torch.cuda.empty_cache()
+        sq = tq.tq_encode(queries[:nrec], xs)
+        s_ids, _ = tq.tq_search_knn(sdb, sq, 10, path=tq.TQ_PATH_PLAIN, engine=tq.TQ_ENGINE_SPARSE)
+        b_ids, b_sc = tq.tq_search_knn(sdb, sq, 10, path=tq.TQ_PATH_PLAIN, engine=tq.TQ_ENGINE_POPCOUNT)
+        s_ids2, s_sc2 = tq.tq_search_knn(sdb, sq, 10, path=tq.TQ_PATH_PLAIN, engine=tq.TQ_ENGINE_SPARSE)
+        torch.cuda.synchronize()
+        same = bool(torch.equal(s_ids2, b_ids) and torch.equal(s_sc2, b_sc))
+        timing = {}
+        for name, eng, fam in (("index_list", tq.TQ_ENGINE_SPARSE, 3), ("bit_planes", tq.TQ_ENGINE_POPCOUNT, 0)):
+            tq.tq_timing_read(fam, reset=True)
+            tq.tq_timing_enable(True)
+            t_s = time.perf_counter()
+            tq.tq_search_knn(sdb, sq, 10, path=tq.TQ_PATH_PLAIN, engine=eng)
+            torch.cuda.synchronize()
+            t_s = time.perf_counter() - t_s
+            tq.tq_timing_enable(False)
+            ms_s, l_s = tq.tq_timing_read(fam, reset=True)
+            timing[name] = (nrec / t_s, ms_s / max(1, l_s), l_s)
+        sc_chunks = (xs + 7) // 8
+        s_bytes = n * 16 * sc_chunks  # 8 two-byte entries per 16-byte chunk, every vector once
+        s_avg = timing["index_list"][1]
+        s_gbps = s_bytes / (s_avg * 1e-3) / 1e9
+        sparse = {"workload": f"same N={n} d={d} vectors encoded at x={xs}, index-list engine, k=10",
+                  "x": xs, "recall_at_10": round(metrics.recall_at(gt_ids, s_ids.cpu().numpy(), 10, 10), 4),
+                  "queries": nrec, "qps": round(timing["index_list"][0], 1),
+                  "bit_planes_qps": round(timing["bit_planes"][0], 1),
+                  "bit_planes_avg_launch_ms": round(timing["bit_planes"][1], 4),
+                  "same_results_as_bit_planes": same,
+                  "roofline": {"kernel": "scan_sparse_kernel", "bound": "hbm", "achieved": round(s_gbps, 1),
+                               "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(s_gbps / HBM_PEAK_GBPS, 4),
+                               "bytes_per_launch": s_bytes, "avg_launch_ms": round(s_avg, 4),
+                               "launches": timing["index_list"][2]}}
+        log(f"index list x={xs}: recall@10 {sparse['recall_at_10']}, {s_avg:.4f} ms per scan "
+            f"({sparse['roofline']['frac'] * 100:.1f}% of HBM), {sparse['qps']} q/s vs "
+            f"{sparse['bit_planes_qps']} q/s on the bit planes, same results: {same}")
+        sdb.destroy()
+        del sq, s_ids, b_ids, b_sc, s_ids2, s_sc2
+        torch.cuda.empty_cache()
 
     # ---- timed steps
     B = args.batch
@@ -453,6 +507,7 @@ def main():
         "recall_queries": nrec,
         "rerank": rerank,
         "masked": masked,
+        "sparse": sparse,
         "encode": {"rows_per_s": round(enc_bytes / (4 * (d + 2 * W)) / (enc_ms * 1e-3), 1),
                    "gbps": round(enc_bytes / (enc_ms * 1e-3) / 1e9, 1)},
         "roofline": {"kernel": "scan_plain_kernel", "bound": "hbm", "achieved": round(achieved, 1),

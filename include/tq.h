@@ -140,7 +140,9 @@ typedef struct tq_db tq_db;
  *          number of them (e.g. tq_encode_b158).
  *
  * The library copies the codes into its own device memory (re-tiled for
- * streaming; the bits are unchanged) and checks every row: exactly x
+ * streaming; the bits are unchanged; with 8x <= d also a second copy as
+ * lists of the non-zero coordinates, see TQ_ENGINE_SPARSE, counted in
+ * tq_db_info's device_bytes) and checks every row: exactly x
  * non-zeros (any number when x = 0), no coordinate in both planes, zero
  * padding bits.  A malformed row gives TQ_ERR_INVALID and no database.
  * Requires 1 <= n < 2^31, 0 <= x <= d.  The
@@ -186,16 +188,25 @@ typedef struct tq_search_opts {
   int use_graph;     /* batched path: 1 = replay a captured hipGraph for the
                         batch-size bucket (default when the struct is NULL),
                         0 = launch the kernels directly */
-  int engine;        /* batched path: TQ_ENGINE_AUTO, TQ_ENGINE_POPCOUNT or
-                        TQ_ENGINE_MATRIX (results are identical) */
+  int engine;        /* TQ_ENGINE_AUTO, or on the batched path
+                        TQ_ENGINE_POPCOUNT or TQ_ENGINE_MATRIX, or
+                        TQ_ENGINE_SPARSE (plain path; AUTO path means plain);
+                        results are identical */
   int reserved[2];
 } tq_search_opts;
 
 enum tq_engine {
   TQ_ENGINE_AUTO = 0,     /* the tuned / default choice */
   TQ_ENGINE_POPCOUNT = 1, /* Delta by AND / XOR / popcount on the vector ALUs */
-  TQ_ENGINE_MATRIX = 2    /* Delta as a ternary matrix product on the fp4 matrix
+  TQ_ENGINE_MATRIX = 2,   /* Delta as a ternary matrix product on the fp4 matrix
                              cores (exact; k <= 128) */
+  TQ_ENGINE_SPARSE = 3    /* plain path: Delta gathered from the query at each
+                             database code's listed non-zeros (a second,
+                             index-list copy that tq_db_create keeps when
+                             8x <= d: 2x bytes per vector instead of d/4;
+                             Sec. 6 leaves small-x speed-ups open).  The plain
+                             path with TQ_ENGINE_AUTO uses it when 16x <= d.
+                             TQ_ERR_INVALID where there is no such copy. */
 };
 
 /* k nearest database codes of each of nq query codes.
@@ -349,7 +360,7 @@ int tq_timing_enable(int enable);
 
 /* Sum of the timed scan-kernel durations since the last reset, and the number
  * of launches, for kernel family `which` (0 = plain scan, 1 = batched scan,
- * 2 = masked-addition scan).
+ * 2 = masked-addition scan, 3 = index-list scan).
  * Waits for the recorded events.  reset != 0 clears the counters. */
 int tq_timing_read(int which, double *total_ms, int64_t *launches, int reset);
 

@@ -322,6 +322,25 @@ int tq_db_create(const uint32_t *codes, int64_t n, int d, int x, void *stream, t
     return hip_fail(e, "database repack");
   }
   db->dev = tqi::DbDev{tiles, n, ntiles, d, x, W, nc};
+  const int sc = tqi::sparse_chunks(d, x);
+  if (sc > 0) {
+    const size_t sbytes = static_cast<size_t>(ntiles) * sc * 64 * sizeof(uint4);
+    uint4 *sp = nullptr;
+    e = hipMalloc(&sp, sbytes);
+    if (e == hipSuccess) {
+      e = tqi::sparse_repack_launch(db->dev, sp, sc, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) (void)hipFree(sp);
+    }
+    if (e != hipSuccess) {
+      (void)hipFree(tiles);
+      delete db;
+      return hip_fail(e, "index-list copy of the database");
+    }
+    db->dev.sparse = sp;
+    db->dev.sc = sc;
+    db->bytes += sbytes;
+  }
   *out = db;
   return TQ_OK;
 }
@@ -354,6 +373,7 @@ int tq_db_destroy(tq_db *db) {
     scratch_free_all(db->scratch);
     batched_release(db);
     if (db->dev.tiles) (void)hipFree(const_cast<uint4 *>(db->dev.tiles));
+    if (db->dev.sparse) (void)hipFree(const_cast<uint4 *>(db->dev.sparse));
   }
   delete db;
   return TQ_OK;
@@ -371,8 +391,13 @@ int tq_search_knn(const tq_db *cdb, const uint32_t *qcodes, int nq, int k, int32
   const int path = opts ? opts->path : TQ_PATH_AUTO;
   if (path < TQ_PATH_AUTO || path > TQ_PATH_BATCHED) return fail(TQ_ERR_INVALID, "unknown path %d", path);
   if (opts && (opts->grid < 0 || opts->qtile < 0)) return fail(TQ_ERR_INVALID, "negative grid or qtile");
-  if (opts && (opts->engine < TQ_ENGINE_AUTO || opts->engine > TQ_ENGINE_MATRIX))
-    return fail(TQ_ERR_INVALID, "unknown engine %d", opts->engine);
+  const int engine = opts ? opts->engine : TQ_ENGINE_AUTO;
+  if (engine < TQ_ENGINE_AUTO || engine > TQ_ENGINE_SPARSE) return fail(TQ_ERR_INVALID, "unknown engine %d", engine);
+  if (engine == TQ_ENGINE_SPARSE) {
+    if (path == TQ_PATH_BATCHED) return fail(TQ_ERR_INVALID, "the index-list engine serves the plain path only");
+    if (!db->dev.sparse)
+      return fail(TQ_ERR_INVALID, "no index-list copy: kept only for 8x <= d (x=%d, d=%d)", db->dev.x, db->dev.d);
+  }
   DeviceGuard g(db->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   int rc;
@@ -384,9 +409,9 @@ int tq_search_knn(const tq_db *cdb, const uint32_t *qcodes, int nq, int k, int32
                   db->dev.d);
   }
   std::lock_guard<std::mutex> l(db->mu);
-  const int use = choose_path(db, path, nq, k);
+  const int use = engine == TQ_ENGINE_SPARSE ? TQ_PATH_PLAIN : choose_path(db, path, nq, k);
   if (use == TQ_PATH_BATCHED) return search_batched(db, qcodes, nq, k, ids, scores, opts, s);
-  return search_plain(db, qcodes, nq, k, ids, scores, opts ? opts->grid : 0, s);
+  return search_plain(db, qcodes, nq, k, ids, scores, opts ? opts->grid : 0, engine, s);
 }
 
 int tq_search_masked(const tq_db *cdb, const float *Q, int nq, int k, int32_t *ids, float *scores,

@@ -309,7 +309,8 @@ int search_batched(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *id
   const bool use_graph = opts ? opts->use_graph != 0 : true;
   const int engine = opts ? opts->engine : TQ_ENGINE_AUTO;
   const int q = opts ? opts->qtile : 0;
-  if (engine < TQ_ENGINE_AUTO || engine > TQ_ENGINE_MATRIX) return fail(TQ_ERR_INVALID, "unknown engine %d", engine);
+  if (engine < TQ_ENGINE_AUTO || engine > TQ_ENGINE_MATRIX)
+    return fail(TQ_ERR_INVALID, "engine %d does not serve the batched path", engine);
   const bool matrix = engine == TQ_ENGINE_MATRIX || (engine == TQ_ENGINE_AUTO && q >= 64);
   if (matrix && tqi::rows_for_k(k) > 2) return fail(TQ_ERR_INVALID, "the matrix engine supports k <= 128 (k=%d)", k);
   if (q > 0) {
@@ -357,7 +358,7 @@ static int time_config(tq_db *db, const uint32_t *q, int nq, int k, int32_t *ids
   for (int rep = 0; rep < 2 && rc == TQ_OK; ++rep) {
     (void)hipEventRecord(a, s);
     if (sh.plain)
-      rc = search_plain(db, q, nq, k, ids, scores, 0, s);
+      rc = search_plain(db, q, nq, k, ids, scores, 0, TQ_ENGINE_AUTO, s);
     else
       rc = run_chunk(db, q, nq, k, ids, scores, sh, true, s);
     (void)hipEventRecord(b, s);

@@ -18,9 +18,19 @@ int default_plain_grid(const tq_db *db) {
   return static_cast<int>(std::max<int64_t>(1, std::min(by_tiles, by_cu)));
 }
 
+// The index-list scan holds few registers and reads at most half the bytes
+// per vector: eight workgroups per compute unit keep enough loads in flight.
+static int default_sparse_grid(const tq_db *db) {
+  const int64_t by_tiles = (db->dev.ntiles + 3) / 4;
+  const int64_t by_cu = static_cast<int64_t>(db->num_cu > 0 ? db->num_cu : 256) * 8;
+  return static_cast<int>(std::max<int64_t>(1, std::min(by_tiles, by_cu)));
+}
+
 int search_plain(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids, int32_t *scores, int grid,
-                 hipStream_t s) {
-  const int G = grid > 0 ? grid : default_plain_grid(db);
+                 int engine, hipStream_t s) {
+  const bool sparse = engine == TQ_ENGINE_SPARSE || (engine == TQ_ENGINE_AUTO && tqi::sparse_preferred(db->dev));
+  if (sparse && !db->dev.sparse) return fail(TQ_ERR_INVALID, "no index-list copy of this database");
+  const int G = grid > 0 ? grid : sparse ? default_sparse_grid(db) : default_plain_grid(db);
   const size_t per_query = static_cast<size_t>(G) * k * sizeof(uint64_t);
   const int chunk = static_cast<int>(std::max<size_t>(1, std::min<size_t>(nq, kPartialBudget / per_query)));
   const size_t mid_keys = static_cast<size_t>(tqi::merge_mid_keys(chunk, G, k));
@@ -33,9 +43,11 @@ int search_plain(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids,
   for (int q0 = 0; q0 < nq; q0 += chunk) {
     const int nc = std::min(chunk, nq - q0);
     for (int i = 0; i < nc; ++i) {
-      TimedLaunch t(kTimePlain, s);
-      hipError_t e = tqi::scan_plain_launch(db->dev, qcodes + static_cast<int64_t>(q0 + i) * row_words, k, G,
-                                            partial + static_cast<size_t>(i) * G * k, s);
+      TimedLaunch t(sparse ? kTimeSparse : kTimePlain, s);
+      const uint32_t *qc = qcodes + static_cast<int64_t>(q0 + i) * row_words;
+      uint64_t *dst = partial + static_cast<size_t>(i) * G * k;
+      hipError_t e = sparse ? tqi::scan_sparse_launch(db->dev, qc, k, G, dst, s)
+                            : tqi::scan_plain_launch(db->dev, qc, k, G, dst, s);
       if (e != hipSuccess) return hip_fail(e, "plain scan launch");
     }
     hipError_t e = tqi::merge_launch(partial, nc, G, k, ids + static_cast<int64_t>(q0) * k,

@@ -34,7 +34,13 @@ struct DbDev {
   int64_t n;
   int64_t ntiles;
   int d, x, W, nc;
+  // Index-list copy (sparse.hip) of a database with 8 x <= d, else null:
+  // sc 16-byte chunks of 8 uint16 entries per vector, tiled like the planes.
+  const uint4 *sparse = nullptr;
+  int sc = 0;
 };
+
+constexpr int kMaxSparseChunks = 16;  // x <= 128 (8 x <= d <= 1024)
 
 // ---------------------------------------------------------------------------
 // Result keys
@@ -96,6 +102,18 @@ hipError_t merge_launch(const uint64_t *partial, int nq, int nlists, int k, int3
                         int32_t *scores, uint64_t *mid, hipStream_t s);
 hipError_t delta_dump_launch(const DbDev &db, const uint32_t *qcodes, int nq, int32_t *out,
                              hipStream_t s);
+
+// sparse.hip: chunks of the index-list copy for (d, x), 0 where none is
+// kept (x = 0 or 8 x > d); the copy is built from the resident bit planes
+// (sc = sparse_chunks(d, x) chunks per vector, ntiles * sc * 64 uint4), and
+// scanned like scan_plain_launch.
+int sparse_chunks(int d, int x);
+hipError_t sparse_repack_launch(const DbDev &db, uint4 *out, int sc, hipStream_t s);
+hipError_t scan_sparse_launch(const DbDev &db, const uint32_t *qcode, int k, int grid, uint64_t *partial,
+                              hipStream_t s);
+// The plain path takes the index-list scan by itself where the list is at
+// most half the bit planes' bytes (2x <= d/8).
+inline bool sparse_preferred(const DbDev &db) { return db.sparse != nullptr && 16 * db.x <= db.d; }
 
 // masked.hip: the masked-addition scan of one float query (d floats, device)
 // against the database, writing `grid` sorted lists of k keys like

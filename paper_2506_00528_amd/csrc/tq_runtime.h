@@ -42,7 +42,7 @@ class DeviceGuard {
 };
 
 // --- kernel timing ----------------------------------------------------------
-enum TimingFamily { kTimePlain = 0, kTimeBatched = 1, kTimeMasked = 2, kTimeFamilies = 3 };
+enum TimingFamily { kTimePlain = 0, kTimeBatched = 1, kTimeMasked = 2, kTimeSparse = 3, kTimeFamilies = 4 };
 
 bool timing_enabled();
 
@@ -92,8 +92,10 @@ namespace tqr {
 
 // search.cpp
 int default_plain_grid(const tq_db *db);
+// engine: TQ_ENGINE_SPARSE takes the index-list scan, TQ_ENGINE_AUTO takes it
+// where sparse_preferred(), anything else the bit-plane scan.
 int search_plain(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids, int32_t *scores, int grid,
-                 hipStream_t s);
+                 int engine, hipStream_t s);
 int search_masked(tq_db *db, const float *Q, int nq, int k, int32_t *ids, float *scores, int grid, hipStream_t s);
 
 // batched.cpp

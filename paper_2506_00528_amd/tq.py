@@ -34,6 +34,7 @@ TQ_PATH_BATCHED = 2
 TQ_ENGINE_AUTO = 0
 TQ_ENGINE_POPCOUNT = 1
 TQ_ENGINE_MATRIX = 2
+TQ_ENGINE_SPARSE = 3
 
 TQ_MAX_D = 1024
 TQ_MAX_K = 512

@@ -87,7 +87,8 @@ def test_masked_host_validation_without_gpu(tq):
     L = tq.lib()
     p = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
     assert L.tq_search_masked(None, p, 1, 1, p, p, None, None) == tq.TQ_ERR_INVALID
-    assert L.tq_timing_read(3, None, None, 0) == tq.TQ_ERR_INVALID
+    assert L.tq_timing_read(3, None, None, 0) == tq.TQ_OK  # index-list scan family
+    assert L.tq_timing_read(4, None, None, 0) == tq.TQ_ERR_INVALID
 
 
 def test_default_x_against_the_oracle(tq):
