@@ -176,8 +176,6 @@ def run_serving(tq, torch, args, log):
     codes = torch.empty((n, 2 * W), dtype=torch.int32, device=dev)
     for r0, X in datagen.iter_rows(wl["spec"], datagen.DB, 0, n, dev):
         tq.tq_encode(X, x, codes[r0:r0 + X.shape[0]])
-        if sp_codes is not None:
-            tq.tq_encode(X, xs, sp_codes[r0:r0 + X.shape[0]])
         gt.add(X, r0)
     tq.tq_sync()
     db = tq.tq_db_create(codes, d, x)
