@@ -153,7 +153,7 @@ __global__ __launch_bounds__(kBatchBlock) void scan_batched_kernel(const uint4 *
             delta_word(a, qw[4 * c + 3], qw[4 * NC + 4 * c + 3], vz[c].w, vg[c].w);
           }
           const uint64_t key = make_key(delta_value(a), static_cast<uint32_t>(id));
-          offer_keys<R>(list[qi], thr[qi], key, ok, km1, lane);
+          offer_keys<R>(list[qi], thr[qi], key, ok, km1);
         }
       }
     }

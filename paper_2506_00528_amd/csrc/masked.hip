@@ -90,7 +90,7 @@ __global__ __launch_bounds__(kMaskedBlock) void scan_masked_kernel(const uint4 *
     const float score = static_cast<float>((sp[0] + sp[1]) - 2.0 * (sm[0] + sm[1]));
     const int64_t id = t * 64 + lane;
     const uint64_t key = make_key(float_rank(score), static_cast<uint32_t>(id));
-    offer_keys<R>(list, thr, key, id < n, km1, lane);
+    offer_keys<R>(list, thr, key, id < n, km1);
   }
 
   uint64_t *a = lds[0];

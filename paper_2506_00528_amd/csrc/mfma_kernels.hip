@@ -219,7 +219,7 @@ __global__ __launch_bounds__(kMfmaBlock, R * RB <= 2 ? 2 : 1) void scan_mfma_ker
                     m &= m - 1;
                     const uint64_t c = readlane64(key, src);
                     if (c > thr) {
-                      list[qi].insert(c, lane);
+                      list[qi].insert(c);
                       thr = list[qi].at(km1);
                     }
                   }
@@ -277,14 +277,15 @@ struct GroupList {
   uint64_t v;
 
   // insert c (this lane's group candidate) where `act`; entries shift down
-  __device__ __forceinline__ void insert(uint64_t c, bool act, int lane) {
-    const uint64_t up = __shfl_up(static_cast<unsigned long long>(v), 1u, 16);
-    const uint64_t prev = (lane & 15) == 0 ? ~0ull : up;
+  __device__ __forceinline__ void insert(uint64_t c, bool act) {
+    const uint64_t prev = dpp_move64<kDppRowShr1>(v, ~0ull);  // lane p - 1 of the group; ~0 at p = 0
     const uint64_t nv = (v > c) ? v : ((prev > c) ? c : prev);
     if (act) v = nv;
   }
 };
 
+// Entry p (uniform) of this lane's group list, given to every lane of the
+// group.
 __device__ __forceinline__ uint64_t group_entry(uint64_t v, int gbase, int p) {
   return __shfl(static_cast<unsigned long long>(v), gbase + p);
 }
@@ -398,7 +399,7 @@ __global__ __launch_bounds__(kMfmaBlock, RB <= 2 ? 2 : 1) void scan_mfma_group_k
                   const uint32_t mg = static_cast<uint32_t>(m >> gbase) & 0xFFFFu;
                   const int src = gbase + __builtin_ctz(mg | 0x10000u);
                   const uint64_t c = __shfl(static_cast<unsigned long long>(key), src & 63);
-                  L.insert(c, mg != 0 && c > thr, lane);
+                  L.insert(c, mg != 0 && c > thr);
                   m &= ~__ballot(mg != 0 && lane == src);
                   thr = group_entry(L.v, gbase, km1);
                   m &= __ballot(key > thr);

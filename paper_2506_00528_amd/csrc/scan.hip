@@ -41,7 +41,7 @@ __global__ __launch_bounds__(kScanBlock) void scan_plain_kernel(const uint4 *__r
     const int32_t delta = tile_delta<NC>(tiles + t * (2 * NC * 64), lane, q);
     const int64_t id = t * 64 + lane;
     const uint64_t key = make_key(delta, static_cast<uint32_t>(id));
-    offer_keys<R>(list, thr, key, id < n, km1, lane);
+    offer_keys<R>(list, thr, key, id < n, km1);
   }
 
   // workgroup merge of the wave lists (positions 0 .. k-1 of each)

@@ -136,7 +136,7 @@ __global__ __launch_bounds__(kSparseBlock) void scan_sparse_kernel(const uint4 *
 #pragma unroll
       for (int c = 0; c < SC; ++c) delta += chunk_sum(tab, cur[c]);
       const int64_t id = t * 64 + lane;
-      offer_keys<R>(list, thr, make_key(delta, static_cast<uint32_t>(id)), id < n, km1, lane);
+      offer_keys<R>(list, thr, make_key(delta, static_cast<uint32_t>(id)), id < n, km1);
 #pragma unroll
       for (int c = 0; c < SC; ++c) cur[c] = nxt[c];
     }

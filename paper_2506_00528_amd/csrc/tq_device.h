@@ -92,11 +92,23 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
   return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
-// Value of lane (l - 1) for lanes 1..63; lane 0 gets `fill`.
-__device__ __forceinline__ uint64_t shift_up1(uint64_t v, uint64_t fill, int lane) {
-  const uint64_t up = __shfl_up(static_cast<unsigned long long>(v), 1u);
-  return lane == 0 ? fill : up;
+// DPP lane moves (one VALU instruction each, no LDS round trip).  A lane
+// whose source lies outside the wave or row keeps `fill`.  Callers run with
+// every lane of the wave active.
+constexpr int kDppWaveShr1 = 0x138;  // lane l takes lane l - 1 of the wave
+constexpr int kDppRowShr1 = 0x111;   // lane l takes lane l - 1 of its row of 16
+
+template <int Ctrl>
+__device__ __forceinline__ uint64_t dpp_move64(uint64_t v, uint64_t fill) {
+  const uint32_t lo = __builtin_amdgcn_update_dpp(static_cast<uint32_t>(fill), static_cast<uint32_t>(v), Ctrl, 0xf,
+                                                  0xf, false);
+  const uint32_t hi = __builtin_amdgcn_update_dpp(static_cast<uint32_t>(fill >> 32), static_cast<uint32_t>(v >> 32),
+                                                  Ctrl, 0xf, 0xf, false);
+  return (static_cast<uint64_t>(hi) << 32) | lo;
 }
+
+// Value of lane (l - 1) for lanes 1..63; lane 0 gets `fill`.
+__device__ __forceinline__ uint64_t shift_up1(uint64_t v, uint64_t fill) { return dpp_move64<kDppWaveShr1>(v, fill); }
 
 // ---------------------------------------------------------------------------
 // Wave-wide sorted list in registers
@@ -123,12 +135,12 @@ struct WaveList {
     return res;
   }
 
-  __device__ __forceinline__ void insert(uint64_t key, int lane) {
+  __device__ __forceinline__ void insert(uint64_t key) {
     uint64_t prev[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const uint64_t carry = (r == 0) ? ~0ull : readlane64(v[r - 1], 63);
-      prev[r] = shift_up1(v[r], carry, lane);
+      prev[r] = shift_up1(v[r], carry);
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -144,14 +156,14 @@ struct WaveList {
 // lane order, i.e. in increasing database id within the tile.
 template <int R>
 __device__ __forceinline__ void offer_keys(WaveList<R> &list, uint64_t &thr, uint64_t key, bool ok,
-                                           int k_minus_1, int lane) {
+                                           int k_minus_1) {
   uint64_t m = __ballot(ok && key > thr);
   while (m) {
     const int src = __builtin_ctzll(m);
     m &= m - 1;
     const uint64_t c = readlane64(key, src);
     if (c > thr) {
-      list.insert(c, lane);
+      list.insert(c);
       thr = list.at(k_minus_1);
     }
   }
