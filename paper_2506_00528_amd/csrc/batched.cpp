@@ -111,12 +111,10 @@ void tune_store(int nc, int k, int bucket, const Shape &s) {
 }  // namespace
 
 // Untuned choice, from measurements on MI355X (N = 1e7, d = 1024): the
-// matrix engine wins from 16 queries for k <= 64 and from 64 queries for
-// k <= 128; the popcount engine below that and for larger k.
+// matrix engine wins from 16 queries for k <= 128; the popcount engine below
+// that and for larger k.
 int default_engine(int k, int nq) {
-  const int r = tqi::rows_for_k(k);
-  if (r == 1 && nq >= 16) return TQ_ENGINE_MATRIX;
-  if (r == 2 && nq >= 64) return TQ_ENGINE_MATRIX;
+  if (tqi::rows_for_k(k) <= 2 && nq >= 16) return TQ_ENGINE_MATRIX;
   return TQ_ENGINE_POPCOUNT;
 }
 
@@ -149,6 +147,7 @@ struct BatchEntry {
   tqi::BatchParams *prm = nullptr;
   uint64_t *partial = nullptr;
   uint64_t *mid = nullptr;  // first-stage merge results
+  uint64_t *bound = nullptr;  // per (query, part) published keys (BatchParams::bound)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -167,6 +166,7 @@ void free_entry(BatchEntry &e) {
   if (e.prm) (void)hipFree(e.prm);
   if (e.partial) (void)hipFree(e.partial);
   if (e.mid) (void)hipFree(e.mid);
+  if (e.bound) (void)hipFree(e.bound);
   e = BatchEntry{};
 }
 
@@ -187,6 +187,7 @@ int get_entry(tq_db *db, hipStream_t s, int bucket, int k, const Shape &sh, Batc
   hipError_t err = hipMalloc(&e.qprep, qbytes);
   if (err == hipSuccess) err = hipMalloc(&e.prm, sizeof(tqi::BatchParams));
   if (err == hipSuccess) err = hipMalloc(&e.partial, lists * k * sizeof(uint64_t));
+  if (err == hipSuccess) err = hipMalloc(&e.bound, lists * sizeof(uint64_t));
   if (err == hipSuccess)
     err = hipMalloc(&e.mid, static_cast<size_t>(tqi::merge_batched_mid_keys(bucket, sh.grid + tqi::kXcds, k)) *
                                 sizeof(uint64_t));
@@ -249,7 +250,7 @@ int run_chunk(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids, in
   int rc = get_entry(db, s, bucket, k, sh, &e);
   if (rc) return rc;
   hipError_t err = tqi::batch_prep_launch(qcodes, nq, bucket, db->dev, sh.qtile, sh.grid, ids, scores, e->qprep,
-                                          e->prm, s);
+                                          e->prm, e->bound, s);
   if (err != hipSuccess) return hip_fail(err, "batch prep launch");
   if (timing_enabled()) {
     // timed runs launch directly so the events bracket the scan kernel alone

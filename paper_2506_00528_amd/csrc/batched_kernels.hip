@@ -44,9 +44,15 @@ __global__ __launch_bounds__(256) void prep_rows_kernel(const uint32_t *__restri
 __global__ __launch_bounds__(256) void batch_prep_kernel(const uint32_t *__restrict__ qcodes, int nq, int bucket,
                                                          int W, int nc, int qtile, int grid, int64_t ntiles,
                                                          int32_t *ids, int32_t *scores, uint32_t *__restrict__ qprep,
-                                                         BatchParams *__restrict__ prm) {
+                                                         BatchParams *__restrict__ prm, uint64_t *__restrict__ bound) {
   const int W4 = 4 * nc;
   const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (bound) {
+    BatchParams b;
+    batch_split(b, nq, qtile, grid, 0, ntiles);
+    const int64_t nb = static_cast<int64_t>(nq) * b.parts;
+    for (int64_t i = g; i < nb; i += static_cast<int64_t>(gridDim.x) * blockDim.x) bound[i] = 0;
+  }
   if (g < static_cast<int64_t>(bucket) * W4) {
     const int q = static_cast<int>(g / W4);
     const int w = static_cast<int>(g - static_cast<int64_t>(q) * W4);
@@ -65,6 +71,7 @@ __global__ __launch_bounds__(256) void batch_prep_kernel(const uint32_t *__restr
     b.running = nullptr;
     b.ids = ids;
     b.scores = scores;
+    b.bound = bound;
     *prm = b;
   }
 }
@@ -218,11 +225,12 @@ int batched_max_qtile(int k) {
 }
 
 hipError_t batch_prep_launch(const uint32_t *qcodes, int nq, int bucket, const DbDev &db, int qtile, int grid,
-                             int32_t *ids, int32_t *scores, uint32_t *qprep, BatchParams *prm, hipStream_t s) {
+                             int32_t *ids, int32_t *scores, uint32_t *qprep, BatchParams *prm, uint64_t *bound,
+                             hipStream_t s) {
   const int64_t threads = static_cast<int64_t>(bucket) * 4 * db.nc;
   const unsigned blocks = static_cast<unsigned>((threads + 255) / 256);
   hipLaunchKernelGGL(batch_prep_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, qcodes, nq, bucket, db.W,
-                     db.nc, qtile, grid, db.ntiles, ids, scores, qprep, prm);
+                     db.nc, qtile, grid, db.ntiles, ids, scores, qprep, prm, bound);
   return hipGetLastError();
 }
 

@@ -65,6 +65,23 @@ __device__ __forceinline__ float score_of(uint64_t thr) {
   return thr ? static_cast<float>(key_score(thr)) : -1e30f;
 }
 
+// Prefilter threshold of a row from its list's k-th key `own` and the bound
+// `lb` published by the other parts.  Keys of this part arrive in increasing
+// id order, so beating `own` takes a larger score; `lb` may come from a part
+// of higher ids, where an equal score with a lower id is a larger key.
+__device__ __forceinline__ float row_threshold(uint64_t own, uint64_t lb) {
+  return lb > own ? static_cast<float>(key_score(lb)) - 0.5f : score_of(own);
+}
+
+// Relaxed loads and stores at device scope: the published keys of other
+// workgroups (on other XCDs) are read around the non-coherent L2s.
+__device__ __forceinline__ uint64_t load_shared_key(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_shared_key(uint64_t *p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Staging of one 64-vector tile.  Thread j reads 16-byte chunks s = j / 64,
 // j / 64 + 4 (< NC) of both planes of vector v = j % 64 -- a wave reads one
 // contiguous 1 KiB run per load -- and re-codes word w of chunk s into the
@@ -115,16 +132,29 @@ __global__ __launch_bounds__(kMfmaBlock, R * RB <= 2 ? 2 : 1) void scan_mfma_ker
   constexpr int QW = 16 * RB;            // queries per wave
   constexpr int QT = kMfmaWaves * QW;    // queries per workgroup tile
   __shared__ v4i op[2][NC * 4 * 64];     // two staged tiles of fp4 operands
+  __shared__ uint64_t lbs[kMfmaWaves * QW];  // each query's bound from the other parts
   const int j = threadIdx.x;
   const int lane = j & 63;
   const int wave = j >> 6;
   const int col = lane & 15;  // operand row / column of this lane
   const int grp = lane >> 4;  // k-block of this lane; also its output row group
+  uint64_t *const lb = lbs + wave * QW;
   const int nq = prm->nq, nqt = prm->nqt, parts = prm->parts;
   const int64_t tpp = prm->tiles_per_part;
   const int64_t tile_lo = prm->tile_lo, tile_hi = prm->tile_hi;
   const int items = nqt * parts;
   const int km1 = k - 1;
+  // Cross-part pruning.  With P parts holding tiles and m = ceil(k / P), if
+  // every part's list holds m keys >= T then the union holds P m >= k keys
+  // >= T, so the query's k-th key overall is >= T, and keys below T can be
+  // dropped by every part without changing the result.  A part's m-th key
+  // only grows, so any value it has published is such a T for that part, and
+  // the smallest published value over the P parts (0 while one has not
+  // published) is a bound for the query.
+  // (64-query tiles only: the 128-query form has no registers to spare)
+  constexpr bool kPrune = RB == 1;
+  constexpr int kLanesPerQuery = 64 / QW;  // lanes that read one query's bounds
+  const bool prune = kPrune && prm->bound != nullptr;
 
   for (int item = blockIdx.x; item < items; item += gridDim.x) {
     int qt, part;
@@ -153,6 +183,7 @@ __global__ __launch_bounds__(kMfmaBlock, R * RB <= 2 ? 2 : 1) void scan_mfma_ker
     WaveList<R> list[QW];
 #pragma unroll
     for (int qi = 0; qi < QW; ++qi) list[qi].clear();
+    if (lane < QW) lb[lane] = 0;
     // tv[rb][i]: k-th score of this lane's output row 16 rb + 4 grp + i;
     // rows past the real queries never pass
     float tv[RB][4];
@@ -207,7 +238,9 @@ __global__ __launch_bounds__(kMfmaBlock, R * RB <= 2 ? 2 : 1) void scan_mfma_ker
                 // lanes of group g carry row 16 rb + 4 g + i
                 const int qi = rb * 16 + 4 * g + i;
                 if (!(rows[rb][i] & (0xFFFFull << (16 * g))) || qi >= nact) continue;
-                uint64_t thr = list[qi].at(km1);
+                const uint64_t lbq = lb[qi];
+                uint64_t own = list[qi].at(km1);
+                uint64_t thr = own > lbq ? own : lbq;
 #pragma unroll
                 for (int cb = 0; cb < 4; ++cb) {  // increasing ids
                   const int64_t id = t * 64 + cb * 16 + col;
@@ -220,11 +253,12 @@ __global__ __launch_bounds__(kMfmaBlock, R * RB <= 2 ? 2 : 1) void scan_mfma_ker
                     const uint64_t c = readlane64(key, src);
                     if (c > thr) {
                       list[qi].insert(c);
-                      thr = list[qi].at(km1);
+                      own = list[qi].at(km1);
+                      thr = own > lbq ? own : lbq;
                     }
                   }
                 }
-                if (grp == g) tv[rb][i] = score_of(thr);
+                if (grp == g) tv[rb][i] = row_threshold(own, lbq);
               }
             }
           }
@@ -233,14 +267,53 @@ __global__ __launch_bounds__(kMfmaBlock, R * RB <= 2 ? 2 : 1) void scan_mfma_ker
       ready.store(nxt, j);
       __syncthreads();
     };
+    // Publish this wave's m-th keys for its part and read its queries'
+    // bounds (lanes kLanesPerQuery q .. + kLanesPerQuery - 1 take query q's
+    // parts).  A row's prefilter threshold takes the new bound the next time
+    // the row has candidates.
+    auto refresh = [&]() {
+      uint64_t *bound = prm->bound;
+      const int peff = static_cast<int>(max<int64_t>(1, min<int64_t>(parts, (tile_hi - tile_lo + tpp - 1) / tpp)));
+      const int mth = (k + peff - 1) / peff;
+#pragma unroll
+      for (int qi = 0; qi < QW; ++qi) {
+        if (qi < nact) {
+          const uint64_t mk = list[qi].at(mth - 1);
+          if (lane == 0 && mk) store_shared_key(bound + static_cast<int64_t>(q0 + qi) * parts + part, mk);
+        }
+      }
+      const int rq = lane / kLanesPerQuery;
+      uint64_t mn = 0;
+      if (rq < nact) {
+        mn = ~0ull;
+        const uint64_t *row = bound + static_cast<int64_t>(q0 + rq) * parts;
+        for (int p = lane % kLanesPerQuery; p < peff; p += kLanesPerQuery) {
+          const uint64_t v = load_shared_key(row + p);
+          mn = v < mn ? v : mn;
+        }
+      }
+#pragma unroll
+      for (int off = 1; off < kLanesPerQuery; off <<= 1) {
+        const uint64_t o = __shfl_xor(static_cast<unsigned long long>(mn), off);
+        mn = o < mn ? o : mn;
+      }
+      if (lane % kLanesPerQuery == 0) lb[rq] = mn;
+      __builtin_amdgcn_wave_barrier();
+    };
     if (t0 < t1) {
       sa.load(tiles, t0, j);
       sb.load(tiles, min(t0 + 1, t1 - 1), j);
       sa.store(op[0], j);
       __syncthreads();
+      // bounds are exchanged after 1, 2, 4, ..., 64 tiles, then every 64
+      int next = 1;
       for (int64_t t = t0; t < t1; t += 2) {
         step(t, op[0], op[1], sa, sb);
         if (t + 1 < t1) step(t + 1, op[1], op[0], sb, sa);
+        if (kPrune && prune && nact > 0 && static_cast<int>(t + 2 - t0) >= next) {
+          refresh();
+          next = next < 64 ? 2 * next : next + 64;
+        }
       }
     }
 

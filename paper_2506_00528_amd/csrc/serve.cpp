@@ -209,6 +209,7 @@ hipError_t enqueue_tick(tq_server *s, TickPlan &p, TickStage &st) {
   b.running_stride = s->k_run;
   b.ids = nullptr;
   b.scores = nullptr;
+  b.bound = nullptr;
   const size_t max_slots = s->slot_used.size();
   std::memcpy(st.host, &b, sizeof b);
   std::memcpy(st.host + sizeof b, p.slots.data(), nq * sizeof(int));

@@ -25,6 +25,11 @@ struct BatchParams {
   int64_t running_stride;  // keys per running row (>= the call's k)
   int32_t *ids;            // caller's outputs, nq x k (when running is null)
   int32_t *scores;
+  uint64_t *bound;         // optional: nq x parts keys, zero before the scan;
+                           // (query, part) publishes there the m-th key of its
+                           // list, m = ceil(k / parts holding tiles), and the
+                           // scan drops keys below the smallest of a query's
+                           // (see scan_mfma_kernel); null: no such pruning
 };
 
 // Work items are (query tile, database part) pairs.  The hardware dispatcher
@@ -63,8 +68,11 @@ __host__ __device__ inline void batch_split(BatchParams &b, int nq, int qtile, i
 // Largest query tile the batched scan supports for this k.
 int batched_max_qtile(int k);
 
+// `bound` (may be null) holds at least nq * parts keys; the prep kernel zeroes
+// them.
 hipError_t batch_prep_launch(const uint32_t *qcodes, int nq, int bucket, const DbDev &db, int qtile, int grid,
-                             int32_t *ids, int32_t *scores, uint32_t *qprep, BatchParams *prm, hipStream_t s);
+                             int32_t *ids, int32_t *scores, uint32_t *qprep, BatchParams *prm, uint64_t *bound,
+                             hipStream_t s);
 hipError_t scan_batched_launch(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile,
                                int grid, uint64_t *partial, hipStream_t s);
 // The same scan on the fp4 matrix cores (mfma_kernels.hip): k <= 128 with
