@@ -42,6 +42,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--workload", default="large", choices=["small", "mid", "large"])
     p.add_argument("--x", type=int, default=0, help="EVP x (default: the workload's)")
+    p.add_argument("--k", type=int, default=0, help="neighbours per query of the timed steps (default: the workload's)")
     p.add_argument("--batch", type=int, default=100, help="queries per step")
     p.add_argument("--path", default="plain", choices=["plain", "batched", "auto"])
     p.add_argument("--engine", default="matrix", choices=["matrix", "popcount"],
@@ -105,13 +106,12 @@ def run_batching(tq, torch, db, queries, x, n, W, plain_qps, args, log):
     dt = time.perf_counter() - t
     total_q = sum(b for b, _ in batches)
     # rooflines on the first 50 batches (direct launches, HIP events around each scan):
-    # the matrix engine on the batches the tuned path gives it (k <= 64 from 16
-    # queries, k <= 128 from 64), against the fp4 MFMA peak, and the popcount
-    # engine on all 50, against the integer VALU peak
+    # the matrix engine on the batches the tuned path gives it (k <= 128 from 16
+    # queries), against the fp4 MFMA peak, and the popcount engine on all 50,
+    # against the integer VALU peak
     nb = min(50, len(batches))
     d_pad = 128 * ((W * 32 + 127) // 128)  # K of the fp4 products (d padded to 128)
-    on_matrix = [i for i in range(nb) if (batches[i][1] <= 64 and batches[i][0] >= 16) or
-                 (batches[i][1] <= 128 and batches[i][0] >= 64)]
+    on_matrix = [i for i in range(nb) if batches[i][1] <= 128 and batches[i][0] >= 16]
 
     def timed(engine, which):
         tq.tq_timing_read(1, reset=True)
@@ -282,7 +282,7 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     wl = datagen.WORKLOADS[args.workload]
-    n, d, k = wl["n"], wl["d"], wl["k"]
+    n, d, k = wl["n"], wl["d"], args.k or wl["k"]
     x = args.x or wl["x"]
     nq_total = wl["nq"]
     spec = wl["spec"]

@@ -20,7 +20,7 @@ constexpr int kScanWaves = 4;
 constexpr int kScanBlock = 64 * kScanWaves;
 
 template <int NC, int R>
-__global__ __launch_bounds__(kScanBlock) void scan_plain_kernel(const uint4 *__restrict__ tiles, int64_t n,
+__global__ __launch_bounds__(kScanBlock, 2) void scan_plain_kernel(const uint4 *__restrict__ tiles, int64_t n,
                                                                int64_t ntiles, int W,
                                                                const uint32_t *__restrict__ qcode, int k,
                                                                uint64_t *__restrict__ partial) {
@@ -37,11 +37,30 @@ __global__ __launch_bounds__(kScanBlock) void scan_plain_kernel(const uint4 *__r
   uint64_t thr = 0;
   const int km1 = k - 1;
 
-  for (int64_t t = static_cast<int64_t>(blockIdx.x) * kScanWaves + wave; t < ntiles; t += nwaves) {
-    const int32_t delta = tile_delta<NC>(tiles + t * (2 * NC * 64), lane, q);
+  // Two tile buffers: the next tile's loads are in flight while the current
+  // one is scored (past the end a wave re-reads the last tile, so the loads
+  // need no branch).
+  auto score = [&](const TileVec<NC> &v, int64_t t) {
+    const int32_t delta = vec_delta<NC>(v, q);
     const int64_t id = t * 64 + lane;
-    const uint64_t key = make_key(delta, static_cast<uint32_t>(id));
-    offer_keys<R>(list, thr, key, id < n, km1);
+    offer_keys<R>(list, thr, make_key(delta, static_cast<uint32_t>(id)), id < n, km1);
+  };
+  const uint4 *last = tiles + (ntiles - 1) * (2 * NC * 64);
+  auto tile_at = [&](int64_t t) { return t < ntiles ? tiles + t * (2 * NC * 64) : last; };
+  int64_t t = static_cast<int64_t>(blockIdx.x) * kScanWaves + wave;
+  if (t < ntiles) {
+    TileVec<NC> a, b;
+    a.load(tile_at(t), lane);
+    while (true) {
+      b.load(tile_at(t + nwaves), lane);
+      score(a, t);
+      t += nwaves;
+      if (t >= ntiles) break;
+      a.load(tile_at(t + nwaves), lane);
+      score(b, t);
+      t += nwaves;
+      if (t >= ntiles) break;
+    }
   }
 
   // workgroup merge of the wave lists (positions 0 .. k-1 of each)

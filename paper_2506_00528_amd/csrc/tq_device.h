@@ -61,6 +61,32 @@ struct QueryWords {
   }
 };
 
+// This lane's vector of one tile: NC 16-byte chunks of each plane.
+template <int NC>
+struct TileVec {
+  u32x4 vz[NC], vg[NC];
+  __device__ __forceinline__ void load(const uint4 *__restrict__ tile, int lane) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      vz[c] = load_stream(tile + c * 64 + lane);
+      vg[c] = load_stream(tile + (NC + c) * 64 + lane);
+    }
+  }
+};
+
+template <int NC>
+__device__ __forceinline__ int32_t vec_delta(const TileVec<NC> &v, const QueryWords<NC> &q) {
+  DeltaAcc a;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    delta_word(a, q.nz[4 * c + 0], q.ng[4 * c + 0], v.vz[c].x, v.vg[c].x);
+    delta_word(a, q.nz[4 * c + 1], q.ng[4 * c + 1], v.vz[c].y, v.vg[c].y);
+    delta_word(a, q.nz[4 * c + 2], q.ng[4 * c + 2], v.vz[c].z, v.vg[c].z);
+    delta_word(a, q.nz[4 * c + 3], q.ng[4 * c + 3], v.vz[c].w, v.vg[c].w);
+  }
+  return delta_value(a);
+}
+
 // Delta of the query against the 64 vectors of one tile (this lane's vector).
 template <int NC>
 __device__ __forceinline__ int32_t tile_delta(const uint4 *__restrict__ tile, int lane,
