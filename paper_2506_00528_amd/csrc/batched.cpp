@@ -120,15 +120,27 @@ int default_engine(int k, int nq) {
 
 namespace {
 
+// Workgroups of the matrix engine that fit on one CU at once: two of four
+// waves for 64-query tiles and for 128-query tiles at k <= 16; one for the
+// eight-wave 128-query tiles of k > 16 and for 256-query tiles.
+int mfma_resident_per_cu(int k, int qtile) {
+  return (qtile == 256 || (qtile == 128 && k > tqi::kGroupMaxK)) ? 1 : 2;
+}
+
+int default_matrix_qtile(int k, int bucket) { return bucket >= (k <= tqi::kGroupMaxK ? 128 : 256) ? 128 : 64; }
+
 Shape default_shape(const tq_db *db, int k, int bucket) {
   Shape s;
-  s.grid = (db->num_cu > 0 ? db->num_cu : 256) * 2;
+  const int cu = db->num_cu > 0 ? db->num_cu : 256;
+  s.grid = cu * 2;
   s.plain = bucket == 1;
   s.engine = default_engine(k, bucket);
   if (s.engine == TQ_ENGINE_MATRIX) {
-    // 128-query tiles for k <= 16 once a bucket fills them (N = 1e7, d = 1024:
-    // 6.5 ms vs 8.7 ms at 1 024 queries); 64 otherwise
-    s.qtile = (k <= tqi::kGroupMaxK && bucket >= 128) ? 128 : 64;
+    // 128-query tiles once a bucket fills them (N = 1e7, d = 1024, 1 024
+    // queries: k = 10 6.1 ms vs 7.6 ms, k = 100 9.6 ms vs 10.5 ms); for k > 16
+    // from 256 queries; 64 otherwise
+    s.qtile = default_matrix_qtile(k, bucket);
+    s.grid = cu * mfma_resident_per_cu(k, s.qtile);
   } else {
     const int qmax = tqi::batched_max_qtile(k);
     s.qtile = std::min(qmax, bucket <= 2 ? 2 : bucket <= 4 ? 4 : bucket <= 8 ? 8 : 16);
@@ -281,16 +293,25 @@ Shape shape_for(tq_db *db, int k, int bucket, const tq_search_opts *opts) {
   int engine = opts ? opts->engine : TQ_ENGINE_AUTO;
   const int qtile = opts ? opts->qtile : 0;
   if (engine == TQ_ENGINE_AUTO && qtile > 0) engine = qtile >= 64 ? TQ_ENGINE_MATRIX : TQ_ENGINE_POPCOUNT;
+  bool changed = false;
   if (engine != TQ_ENGINE_AUTO && engine != sh.engine) {
     sh.engine = engine;
+    changed = true;
     if (engine == TQ_ENGINE_MATRIX) {
-      sh.qtile = (k <= tqi::kGroupMaxK && bucket >= 128) ? 128 : 64;
+      sh.qtile = default_matrix_qtile(k, bucket);
     } else {
       const int qmax = tqi::batched_max_qtile(k);
       sh.qtile = std::min(qmax, bucket <= 2 ? 2 : bucket <= 4 ? 4 : bucket <= 8 ? 8 : 16);
     }
   }
-  if (qtile > 0) sh.qtile = qtile;
+  if (qtile > 0 && qtile != sh.qtile) {
+    sh.qtile = qtile;
+    changed = true;
+  }
+  if (changed) {
+    const int cu = db->num_cu > 0 ? db->num_cu : 256;
+    sh.grid = sh.engine == TQ_ENGINE_MATRIX ? cu * mfma_resident_per_cu(k, sh.qtile) : cu * 2;
+  }
   if (opts && opts->grid > 0) sh.grid = opts->grid;
   return sh;
 }
@@ -421,10 +442,10 @@ int autotune(tq_db *db, int nq_max, const int *ks, int nks, hipStream_t s, int v
         }
       }
       // matrix engine: the query tiles the bucket can fill, on 1x / 2x the
-      // workgroups that fit at once (two per CU for 64 / 128, one for 256)
+      // workgroups that fit at once
       for (int qt : {64, 128, 256}) {
         if (!tqi::mfma_supported(k, qt) || (qt > 64 && b <= qt / 2)) continue;
-        const int resident = cu * (qt == 256 ? 1 : 2);
+        const int resident = cu * mfma_resident_per_cu(k, qt);
         for (int gm : {1, 2}) {
           Shape c;
           c.engine = TQ_ENGINE_MATRIX;

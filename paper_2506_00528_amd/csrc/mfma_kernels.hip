@@ -89,9 +89,9 @@ __device__ __forceinline__ void store_shared_key(uint64_t *p, uint64_t v) {
 // at K-step s.  The loads are ordinary (cached) loads: the workgroups that
 // scan the same database part for other query tiles run at the same time on
 // the same XCD and find the tile in its L2.
-template <int NC>
+template <int NC, int WV = kMfmaWaves>
 struct TileStage {
-  static constexpr int kPer = (NC + 3) / 4;
+  static constexpr int kPer = (NC + WV - 1) / WV;
   uint4 nz[kPer], ng[kPer];
 
   // Every thread issues the same loads (a chunk past NC re-reads chunk
@@ -101,7 +101,7 @@ struct TileStage {
     const int v = j & 63, s0 = j >> 6;
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
-      const int s = min(s0 + 4 * i, NC - 1);
+      const int s = min(s0 + WV * i, NC - 1);
       nz[i] = tiles[((t * 2 + 0) * NC + s) * 64 + v];
       ng[i] = tiles[((t * 2 + 1) * NC + s) * 64 + v];
     }
@@ -112,7 +112,7 @@ struct TileStage {
     v4i *dst = op + (v >> 4) * 64 + (v & 15);
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
-      const int s = s0 + 4 * i;
+      const int s = s0 + WV * i;
       if (s < NC) {
         dst[s * 256 + 0] = fp4_operand(nz[i].x, ng[i].x);
         dst[s * 256 + 16] = fp4_operand(nz[i].y, ng[i].y);
@@ -124,15 +124,15 @@ struct TileStage {
 };
 
 // Two workgroups per CU (their LDS fits) wherever the registers allow it.
-template <int NC, int R, int RB>
-__global__ __launch_bounds__(kMfmaBlock, R * RB <= 2 ? 2 : 1) void scan_mfma_kernel(const uint4 *__restrict__ tiles, int64_t n,
+template <int NC, int R, int RB, int WV>
+__global__ __launch_bounds__(64 * WV, R * RB * WV <= 8 ? 8 / WV : 1) void scan_mfma_kernel(const uint4 *__restrict__ tiles, int64_t n,
                                                               const uint32_t *__restrict__ qprep,
                                                               const BatchParams *__restrict__ prm, int k,
                                                               uint64_t *__restrict__ partial) {
   constexpr int QW = 16 * RB;            // queries per wave
-  constexpr int QT = kMfmaWaves * QW;    // queries per workgroup tile
+  constexpr int QT = WV * QW;            // queries per workgroup tile
   __shared__ v4i op[2][NC * 4 * 64];     // two staged tiles of fp4 operands
-  __shared__ uint64_t lbs[kMfmaWaves * QW];  // each query's bound from the other parts
+  __shared__ uint64_t lbs[WV * QW];      // each query's bound from the other parts
   const int j = threadIdx.x;
   const int lane = j & 63;
   const int wave = j >> 6;
@@ -196,8 +196,8 @@ __global__ __launch_bounds__(kMfmaBlock, R * RB <= 2 ? 2 : 1) void scan_mfma_ker
     // during the previous tile) is re-coded into the other LDS buffer and
     // tile t + 2 is in flight to registers.  Loads past the part re-read its
     // last tile, so every thread issues the same loads on every step.
-    TileStage<NC> sa, sb;
-    auto step = [&](int64_t t, const v4i *cur, v4i *nxt, TileStage<NC> &fill, const TileStage<NC> &ready) {
+    TileStage<NC, WV> sa, sb;
+    auto step = [&](int64_t t, const v4i *cur, v4i *nxt, TileStage<NC, WV> &fill, const TileStage<NC, WV> &ready) {
       fill.load(tiles, min(t + 2, t1 - 1), j);
       if (nact > 0) {
         v4f acc[RB][4];
@@ -517,10 +517,10 @@ hipError_t launch_g(const DbDev &db, const uint32_t *qprep, const BatchParams *p
   return hipGetLastError();
 }
 
-template <int NC, int R, int RB>
+template <int NC, int R, int RB, int WV = kMfmaWaves>
 hipError_t launch_m3(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int grid,
                      uint64_t *partial, hipStream_t s) {
-  hipLaunchKernelGGL((scan_mfma_kernel<NC, R, RB>), dim3(grid), dim3(kMfmaBlock), 0, s, db.tiles, db.n, qprep, prm,
+  hipLaunchKernelGGL((scan_mfma_kernel<NC, R, RB, WV>), dim3(grid), dim3(64 * WV), 0, s, db.tiles, db.n, qprep, prm,
                      k, partial);
   return hipGetLastError();
 }
@@ -538,8 +538,9 @@ hipError_t scan_mfma_launch_nc(const DbDev &db, const uint32_t *qprep, const Bat
   const int r = rows_for_k(k);
   if (qtile == 64) return r == 1 ? launch_m3<NC, 1, 1>(db, qprep, prm, k, grid, partial, s)
                                  : launch_m3<NC, 2, 1>(db, qprep, prm, k, grid, partial, s);
-  return r == 1 ? launch_m3<NC, 1, 2>(db, qprep, prm, k, grid, partial, s)
-                : launch_m3<NC, 2, 2>(db, qprep, prm, k, grid, partial, s);
+  // 128-query tiles: eight waves of 16 queries share each staged tile
+  return r == 1 ? launch_m3<NC, 1, 1, 8>(db, qprep, prm, k, grid, partial, s)
+                : launch_m3<NC, 2, 1, 8>(db, qprep, prm, k, grid, partial, s);
 }
 
 // This file is compiled once per plane width (-DTQ_NC=1..8), so that the
