@@ -127,7 +127,10 @@ int mfma_resident_per_cu(int k, int qtile) {
   return (qtile == 256 || (qtile == 128 && k > tqi::kGroupMaxK)) ? 1 : 2;
 }
 
-int default_matrix_qtile(int k, int bucket) { return bucket >= (k <= tqi::kGroupMaxK ? 128 : 256) ? 128 : 64; }
+int default_matrix_qtile(int k, int bucket) {
+  if (k <= tqi::kGroupMaxK) return bucket >= 256 ? 256 : bucket >= 128 ? 128 : 64;
+  return bucket >= 256 ? 128 : 64;
+}
 
 Shape default_shape(const tq_db *db, int k, int bucket) {
   Shape s;
@@ -136,9 +139,9 @@ Shape default_shape(const tq_db *db, int k, int bucket) {
   s.plain = bucket == 1;
   s.engine = default_engine(k, bucket);
   if (s.engine == TQ_ENGINE_MATRIX) {
-    // 128-query tiles once a bucket fills them (N = 1e7, d = 1024, 1 024
-    // queries: k = 10 6.1 ms vs 7.6 ms, k = 100 9.6 ms vs 10.5 ms); for k > 16
-    // from 256 queries; 64 otherwise
+    // the largest tile a bucket fills (N = 1e7, d = 1024, 1 024 queries:
+    // k = 10 5.2 / 6.1 / 7.5 ms on 256 / 128 / 64-query tiles; k = 100 9.6 ms
+    // vs 10.5 ms on 128 / 64), for k > 16 from 256 queries
     s.qtile = default_matrix_qtile(k, bucket);
     s.grid = cu * mfma_resident_per_cu(k, s.qtile);
   } else {

@@ -342,8 +342,10 @@ __global__ __launch_bounds__(64 * WV, R * RB * WV <= 8 ? 8 / WV : 1) void scan_m
 // lives in exactly those lanes -- entry l % 16 of the list of row
 // 4 (l / 16) + i sits in register i of lane l -- so a list costs a quarter of a
 // register pair, the four groups insert their own candidates at the same
-// time, and a wave can hold 16 RB queries with RB up to 4 (256 queries per
-// workgroup, four times the operand reuse of a 64-query tile).
+// time, and a wave holds 16 RB queries: 64- and 128-query tiles are four
+// waves with RB = 1 or 2, 256-query tiles eight waves with RB = 2 (twice the
+// operand reuse of a 64-query tile in every wave, and half the staging work
+// per thread).
 
 // 16 keys per group, descending; empty entries are 0.
 struct GroupList {
@@ -363,13 +365,13 @@ __device__ __forceinline__ uint64_t group_entry(uint64_t v, int gbase, int p) {
   return __shfl(static_cast<unsigned long long>(v), gbase + p);
 }
 
-template <int NC, int RB>
-__global__ __launch_bounds__(kMfmaBlock, RB <= 2 ? 2 : 1) void scan_mfma_group_kernel(const uint4 *__restrict__ tiles, int64_t n,
+template <int NC, int RB, int WV>
+__global__ __launch_bounds__(64 * WV, RB * WV <= 8 ? 8 / WV : 1) void scan_mfma_group_kernel(const uint4 *__restrict__ tiles, int64_t n,
                                                                     const uint32_t *__restrict__ qprep,
                                                                     const BatchParams *__restrict__ prm, int k,
                                                                     uint64_t *__restrict__ partial) {
   constexpr int QW = 16 * RB;
-  constexpr int QT = kMfmaWaves * QW;
+  constexpr int QT = WV * QW;
   __shared__ v4i op[2][NC * 4 * 64];
   const int j = threadIdx.x;
   const int lane = j & 63;
@@ -418,8 +420,8 @@ __global__ __launch_bounds__(kMfmaBlock, RB <= 2 ? 2 : 1) void scan_mfma_group_k
         tv[rb][i] = (rb * 16 + 4 * grp + i < nact) ? -1e30f : 1e30f;
       }
 
-    TileStage<NC> sa, sb;
-    auto step = [&](int64_t t, const v4i *cur, v4i *nxt, TileStage<NC> &fill, const TileStage<NC> &ready) {
+    TileStage<NC, WV> sa, sb;
+    auto step = [&](int64_t t, const v4i *cur, v4i *nxt, TileStage<NC, WV> &fill, const TileStage<NC, WV> &ready) {
       fill.load(tiles, min(t + 2, t1 - 1), j);
       if (nact > 0) {
         v4f acc[RB][4];
@@ -509,10 +511,10 @@ __global__ __launch_bounds__(kMfmaBlock, RB <= 2 ? 2 : 1) void scan_mfma_group_k
   }
 }
 
-template <int NC, int RB>
+template <int NC, int RB, int WV = kMfmaWaves>
 hipError_t launch_g(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int grid,
                     uint64_t *partial, hipStream_t s) {
-  hipLaunchKernelGGL((scan_mfma_group_kernel<NC, RB>), dim3(grid), dim3(kMfmaBlock), 0, s, db.tiles, db.n, qprep,
+  hipLaunchKernelGGL((scan_mfma_group_kernel<NC, RB, WV>), dim3(grid), dim3(64 * WV), 0, s, db.tiles, db.n, qprep,
                      prm, k, partial);
   return hipGetLastError();
 }
@@ -533,7 +535,7 @@ hipError_t scan_mfma_launch_nc(const DbDev &db, const uint32_t *qprep, const Bat
   if (k <= kGroupMaxK) {
     if (qtile == 64) return launch_g<NC, 1>(db, qprep, prm, k, grid, partial, s);
     if (qtile == 128) return launch_g<NC, 2>(db, qprep, prm, k, grid, partial, s);
-    return launch_g<NC, 4>(db, qprep, prm, k, grid, partial, s);
+    return launch_g<NC, 2, 8>(db, qprep, prm, k, grid, partial, s);  // 256: eight waves of 32
   }
   const int r = rows_for_k(k);
   if (qtile == 64) return r == 1 ? launch_m3<NC, 1, 1>(db, qprep, prm, k, grid, partial, s)
