@@ -235,3 +235,32 @@ def test_matrix_rejects(tq, small):
         tq.tq_search_knn(small["db"], q, 17, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_MATRIX, qtile=256)
     with pytest.raises(tq.TQError):
         tq.tq_search_knn(small["db"], q, 10, path=tq.TQ_PATH_BATCHED, engine=7)
+
+
+@pytest.mark.parametrize("qtile", [64, 128])
+@pytest.mark.parametrize("grid", [64, 256, 512])
+def test_matrix_cross_part_bound_adversarial(tq, o, qtile, grid):
+    """The parts of a query share a lower bound on its k-th key and drop keys
+    below it.  Here each planted query's 52 exact copies (Delta = x) sit in
+    three places -- 6 among the lowest ids, 40 in one contiguous block in the
+    middle, 6 among the highest ids -- so one part holds most of the top-k,
+    parts of higher ids publish bounds with the top score, and the order among
+    the copies is decided by the ids alone: the lowest-id copies must win on
+    every grid and tile."""
+    rng = np.random.default_rng(31 + grid + qtile)
+    d, x, n = 256, 64, 30000
+    V = o.encode(rng.standard_normal((n, d)).astype(np.float32), x)
+    planted = o.encode(rng.standard_normal((8, d)).astype(np.float32), x)
+    for j in range(8):
+        V[j * 6:j * 6 + 6] = planted[j]                     # 6 copies among the lowest ids
+        V[12000 + j * 40:12000 + j * 40 + 40] = planted[j]  # 40 in one middle block
+        V[n - 48 + j * 6:n - 48 + j * 6 + 6] = planted[j]   # 6 among the highest ids
+    VQ = np.concatenate([planted, o.encode(rng.standard_normal((40, d)).astype(np.float32), x)])
+    db = tq.tq_db_create(dev_codes(o.pack(V)), d, x)
+    for k in (17, 50, 100, 128):
+        say(f"matrix bound adversarial qtile={qtile} grid={grid} k={k}")
+        ids, sc = run(tq, db, o.pack(VQ), k, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_MATRIX, qtile=qtile,
+                      grid=grid)
+        ei, es = o.knn(VQ, V, k)
+        assert np.array_equal(sc, es) and np.array_equal(ids, ei), k
+    db.destroy()
