@@ -19,11 +19,17 @@ namespace {
 constexpr int kScanWaves = 4;
 constexpr int kScanBlock = 64 * kScanWaves;
 
+// `tstride` > 1 scans only every tstride-th tile (a sample of the database).
+// With `floor_at` (the result row of a sample scan of this query, k ids then
+// k scores), keys below the sample's k-th key are dropped from the start: the
+// k-th key of a subset is never above the k-th key of the whole database.
 template <int NC, int R>
 __global__ __launch_bounds__(kScanBlock, 2) void scan_plain_kernel(const uint4 *__restrict__ tiles, int64_t n,
                                                                int64_t ntiles, int W,
                                                                const uint32_t *__restrict__ qcode, int k,
-                                                               uint64_t *__restrict__ partial) {
+                                                               uint64_t *__restrict__ partial, int tstride,
+                                                               const int32_t *__restrict__ floor_ids,
+                                                               const int32_t *__restrict__ floor_scores) {
   __shared__ uint64_t lds[2][kScanWaves * 64 * R];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -34,19 +40,23 @@ __global__ __launch_bounds__(kScanBlock, 2) void scan_plain_kernel(const uint4 *
 
   WaveList<R> list;
   list.clear();
-  uint64_t thr = 0;
+  uint64_t floor = 0;  // keys below the sample's k-th key are outside the result
+  if (floor_ids && floor_ids[k - 1] >= 0)
+    floor = make_key(floor_scores[k - 1], static_cast<uint32_t>(floor_ids[k - 1])) - 1;
+  uint64_t thr = floor;
   const int km1 = k - 1;
+  ntiles = (ntiles + tstride - 1) / tstride;  // tiles of this scan: t * tstride
 
   // Two tile buffers: the next tile's loads are in flight while the current
   // one is scored (past the end a wave re-reads the last tile, so the loads
   // need no branch).
   auto score = [&](const TileVec<NC> &v, int64_t t) {
     const int32_t delta = vec_delta<NC>(v, q);
-    const int64_t id = t * 64 + lane;
-    offer_keys<R>(list, thr, make_key(delta, static_cast<uint32_t>(id)), id < n, km1);
+    const int64_t id = t * tstride * 64 + lane;
+    offer_keys<R>(list, thr, make_key(delta, static_cast<uint32_t>(id)), id < n, km1, floor);
   };
-  const uint4 *last = tiles + (ntiles - 1) * (2 * NC * 64);
-  auto tile_at = [&](int64_t t) { return t < ntiles ? tiles + t * (2 * NC * 64) : last; };
+  const uint4 *last = tiles + ((ntiles - 1) * tstride) * (2 * NC * 64);
+  auto tile_at = [&](int64_t t) { return t < ntiles ? tiles + (t * tstride) * (2 * NC * 64) : last; };
   int64_t t = static_cast<int64_t>(blockIdx.x) * kScanWaves + wave;
   if (t < ntiles) {
     TileVec<NC> a, b;
@@ -173,20 +183,20 @@ __global__ __launch_bounds__(256) void delta_dump_kernel(const uint4 *__restrict
 
 template <int NC, int R>
 hipError_t scan_nc_r(const DbDev &db, const uint32_t *qcode, int k, int grid, uint64_t *partial,
-                     hipStream_t s) {
+                     const PlainScanOpts &o, hipStream_t s) {
   hipLaunchKernelGGL((scan_plain_kernel<NC, R>), dim3(grid), dim3(kScanBlock), 0, s, db.tiles, db.n,
-                     db.ntiles, db.W, qcode, k, partial);
+                     db.ntiles, db.W, qcode, k, partial, o.tstride, o.floor_ids, o.floor_scores);
   return hipGetLastError();
 }
 
 template <int NC>
 hipError_t scan_nc(const DbDev &db, const uint32_t *qcode, int k, int grid, uint64_t *partial,
-                   hipStream_t s) {
+                   const PlainScanOpts &o, hipStream_t s) {
   switch (rows_for_k(k)) {
-    case 1: return scan_nc_r<NC, 1>(db, qcode, k, grid, partial, s);
-    case 2: return scan_nc_r<NC, 2>(db, qcode, k, grid, partial, s);
-    case 4: return scan_nc_r<NC, 4>(db, qcode, k, grid, partial, s);
-    default: return scan_nc_r<NC, 8>(db, qcode, k, grid, partial, s);
+    case 1: return scan_nc_r<NC, 1>(db, qcode, k, grid, partial, o, s);
+    case 2: return scan_nc_r<NC, 2>(db, qcode, k, grid, partial, o, s);
+    case 4: return scan_nc_r<NC, 4>(db, qcode, k, grid, partial, o, s);
+    default: return scan_nc_r<NC, 8>(db, qcode, k, grid, partial, o, s);
   }
 }
 
@@ -201,16 +211,17 @@ hipError_t dump_nc(const DbDev &db, const uint32_t *qcodes, int nq, int32_t *out
 }  // namespace
 
 hipError_t scan_plain_launch(const DbDev &db, const uint32_t *qcode, int k, int grid, uint64_t *partial,
-                             hipStream_t s) {
+                             hipStream_t s, const PlainScanOpts &o) {
+  if (o.tstride < 1) return hipErrorInvalidValue;
   switch (db.nc) {
-    case 1: return scan_nc<1>(db, qcode, k, grid, partial, s);
-    case 2: return scan_nc<2>(db, qcode, k, grid, partial, s);
-    case 3: return scan_nc<3>(db, qcode, k, grid, partial, s);
-    case 4: return scan_nc<4>(db, qcode, k, grid, partial, s);
-    case 5: return scan_nc<5>(db, qcode, k, grid, partial, s);
-    case 6: return scan_nc<6>(db, qcode, k, grid, partial, s);
-    case 7: return scan_nc<7>(db, qcode, k, grid, partial, s);
-    case 8: return scan_nc<8>(db, qcode, k, grid, partial, s);
+    case 1: return scan_nc<1>(db, qcode, k, grid, partial, o, s);
+    case 2: return scan_nc<2>(db, qcode, k, grid, partial, o, s);
+    case 3: return scan_nc<3>(db, qcode, k, grid, partial, o, s);
+    case 4: return scan_nc<4>(db, qcode, k, grid, partial, o, s);
+    case 5: return scan_nc<5>(db, qcode, k, grid, partial, o, s);
+    case 6: return scan_nc<6>(db, qcode, k, grid, partial, o, s);
+    case 7: return scan_nc<7>(db, qcode, k, grid, partial, o, s);
+    case 8: return scan_nc<8>(db, qcode, k, grid, partial, o, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -178,11 +178,12 @@ struct WaveList {
 };
 
 // Offer this lane's key (valid only where `ok`) to the wave's list; `thr` is
-// the current k-th key (uniform), updated in place.  Candidates are taken in
-// lane order, i.e. in increasing database id within the tile.
+// the current k-th key (uniform), updated in place, and never below `floor`
+// (keys at or below it are known to be outside the result).  Candidates are
+// taken in lane order, i.e. in increasing database id within the tile.
 template <int R>
 __device__ __forceinline__ void offer_keys(WaveList<R> &list, uint64_t &thr, uint64_t key, bool ok,
-                                           int k_minus_1) {
+                                           int k_minus_1, uint64_t floor = 0) {
   uint64_t m = __ballot(ok && key > thr);
   while (m) {
     const int src = __builtin_ctzll(m);
@@ -191,6 +192,7 @@ __device__ __forceinline__ void offer_keys(WaveList<R> &list, uint64_t &thr, uin
     if (c > thr) {
       list.insert(c);
       thr = list.at(k_minus_1);
+      if (thr < floor) thr = floor;
     }
   }
 }

@@ -91,9 +91,17 @@ hipError_t validate_launch(const uint32_t *codes, int64_t n, int d, int x,
 
 // scan.hip
 // One query against the whole database; `grid` workgroups, each writing one
-// sorted list of k keys to partial[block * k ...].
+// sorted list of k keys to partial[block * k ...].  Options: tstride > 1
+// scans every tstride-th tile only (a sample); floor_ids / floor_scores (k
+// each: a sample scan's result row for this query, device) let the scan drop
+// keys below that row's k-th key.
+struct PlainScanOpts {
+  int tstride = 1;
+  const int32_t *floor_ids = nullptr;
+  const int32_t *floor_scores = nullptr;
+};
 hipError_t scan_plain_launch(const DbDev &db, const uint32_t *qcode, int k, int grid,
-                             uint64_t *partial, hipStream_t s);
+                             uint64_t *partial, hipStream_t s, const PlainScanOpts &o = PlainScanOpts());
 // For each of nq queries, merge its `nlists` sorted lists of k keys (laid out
 // partial[(q * nlists + l) * k + i]) into the final ids / scores.  `mid`
 // holds merge_mid_keys(nq, nlists, k) keys of scratch (may be null when 0).

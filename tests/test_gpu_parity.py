@@ -264,3 +264,31 @@ def test_search_rejects_bad_args(tq, o, small):
     with pytest.raises(tq.TQError) as e:
         tq.tq_search_knn(small["db"], qb, 5, check_queries=True)
     assert e.value.status == tq.TQ_ERR_INVALID
+
+
+@pytest.mark.parametrize("grid", [0, 37])
+def test_search_sample_floor_large_k(tq, o, grid):
+    """k > 128 on a database of >= 2 048 tiles: the plain path first scans a
+    sample (every 32nd tile) and the full scan drops keys below the sample's
+    k-th key (k = 65 and 100 check the same database without a sample).  Each planted query has copies (Delta = x) only in tiles the
+    sample skips plus one in sampled tile 0, and every code has many exact
+    duplicates, so the sample's k-th key ties with keys of lower and higher
+    ids elsewhere; the result must still be the oracle's."""
+    rng = np.random.default_rng(41 + grid)
+    n, d, x = 200_000, 256, 64
+    base = o.encode(rng.standard_normal((3000, d)).astype(np.float32), x)
+    V = base[rng.integers(0, 3000, size=n)]  # ~67 copies of every code
+    planted = o.encode(rng.standard_normal((4, d)).astype(np.float32), x)
+    for j in range(4):
+        V[j] = planted[j]  # tile 0 is sampled
+        for c in range(30):
+            t = 1 + 32 * (c + 1) + j  # tiles the sample skips
+            V[t * 64 + 5] = planted[j]
+    VQ = np.concatenate([planted, base[:4], o.encode(rng.standard_normal((4, d)).astype(np.float32), x)])
+    db = make_db(tq, o.pack(V), d, x)
+    for k in (65, 100, 200, 512):
+        say(f"sample floor n={n} k={k} grid={grid}")
+        ids, sc = search(tq, db, o.pack(VQ), k, path=tq.TQ_PATH_PLAIN, grid=grid)
+        ei, es = o.knn(VQ, V, k)
+        assert np.array_equal(sc, es) and np.array_equal(ids, ei), k
+    db.destroy()
