@@ -63,6 +63,7 @@ def parse():
     p.add_argument("--no-batching", action="store_true", help="skip the batching workload")
     p.add_argument("--batches", type=int, default=500)
     p.add_argument("--no-serving", action="store_true", help="skip the serving workload")
+    p.add_argument("--no-mid", action="store_true", help="skip the mid-workload x sweep")
     p.add_argument("--serve-requests", type=int, default=2000, help="requests per arrival rate")
     p.add_argument("--serve-segments", type=int, default=0, help="database segments per pass (0: library default)")
     return p.parse_args()
@@ -159,6 +160,60 @@ def run_batching(tq, torch, db, queries, x, n, W, plain_qps, args, log):
                                   "peak": round(valu_peak, 2), "unit": "Tops/s", "frac": round(tops / valu_peak, 4),
                                   "ops_per_pair": ops_per_pair, "batches": nb, "launches": launches_p,
                                   "avg_launch_ms": round(kms_p / max(1, launches_p), 4)}}
+
+
+def run_mid_sweep(tq, torch, args, log):
+    """Mid workload (N=1e6, d=768, anisotropic 1 024-component mixture): the x
+    sweep {96, 192, 384} -- recall@10 and 10@100 against the FP64 exact-cosine
+    top-10 of 200 queries, and the plain path's queries/s at k=100 over the
+    1 000 queries.  The 192 MB database fits the 256 MB Infinity Cache, so the
+    scan rate is an effective GB/s, not an HBM figure."""
+    from workloads import datagen, metrics
+    wl = datagen.WORKLOADS["mid"]
+    dev = torch.device("cuda", 0)
+    n, d, k, xs = wl["n"], wl["d"], wl["k"], wl["xs"]
+    W = tq.tq_code_words(d)
+    queries = datagen.rows(wl["spec"], datagen.QUERIES, 0, wl["nq"], dev)
+    nrec = wl["recall_nq"]
+    gt = metrics.ExactTopK(queries[:nrec], 10)
+    codes = {x: torch.empty((n, 2 * W), dtype=torch.int32, device=dev) for x in xs}
+    for r0, X in datagen.iter_rows(wl["spec"], datagen.DB, 0, n, dev):
+        for x in xs:
+            tq.tq_encode(X, x, codes[x][r0:r0 + X.shape[0]])
+        gt.add(X, r0)
+    tq.tq_sync()
+    gt_ids, _ = gt.result()
+    out = {"workload": f"mid: N={n} d={d}, {wl['nq']} queries, k={k}, plain path; recall on {nrec} queries",
+           "rows": []}
+    for x in xs:
+        db = tq.tq_db_create(codes[x], d, x)
+        codes[x] = None
+        q = tq.tq_encode(queries, x)
+        i10, _ = tq.tq_search_knn(db, q[:nrec], 10, path=tq.TQ_PATH_PLAIN)
+        i100, _ = tq.tq_search_knn(db, q[:nrec], 100, path=tq.TQ_PATH_PLAIN)
+        ids = torch.empty((q.shape[0], k), dtype=torch.int32, device=dev)
+        sc = torch.empty_like(ids)
+        tq.tq_search_knn(db, q[:16], k, path=tq.TQ_PATH_PLAIN, ids=ids[:16], scores=sc[:16])
+        torch.cuda.synchronize()
+        tq.tq_timing_read(0, reset=True)
+        tq.tq_timing_enable(True)
+        t0 = time.perf_counter()
+        tq.tq_search_knn(db, q, k, path=tq.TQ_PATH_PLAIN, ids=ids, scores=sc)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        tq.tq_timing_enable(False)
+        kms, launches = tq.tq_timing_read(0, reset=True)
+        avg = kms / max(1, launches)
+        row = {"x": x, "recall_at_10": round(metrics.recall_at(gt_ids, i10.cpu().numpy(), 10, 10), 4),
+               "recall_10_at_100": round(metrics.recall_at(gt_ids, i100.cpu().numpy(), 10, 100), 4),
+               "qps": round(q.shape[0] / dt, 1), "avg_launch_ms": round(avg, 4),
+               "effective_gbps": round(n * 8 * W / (avg * 1e-3) / 1e9, 1)}
+        out["rows"].append(row)
+        log(f"mid x={x}: recall@10 {row['recall_at_10']}, 10@100 {row['recall_10_at_100']}, "
+            f"{row['qps']} q/s at k={k} ({row['avg_launch_ms']} ms per scan)")
+        db.destroy()
+    torch.cuda.empty_cache()
+    return out
 
 
 def run_serving(tq, torch, args, log):
@@ -571,6 +626,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_serving and args.workload == "large":
         result["serving"] = run_serving(tq, torch, args, log)
+    if not args.no_mid and args.workload == "large":
+        result["mid_sweep"] = run_mid_sweep(tq, torch, args, log)
     print(json.dumps(result), flush=True)
 
 
