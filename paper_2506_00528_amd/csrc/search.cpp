@@ -8,13 +8,20 @@ namespace tqr {
 namespace {
 // Partial lists of one merge round stay under this many bytes of scratch.
 constexpr size_t kPartialBudget = size_t(64) << 20;
-// Sample scans for k > 128: every 32nd tile, on databases of at least 2 048
-// tiles (the sample then holds >= 4 096 vectors, eight times the largest k).
-// On N = 1e7, d = 1024 they take k = 512 from about 0.95 ms to 0.49 ms per
-// query and k = 200 to 0.44 ms; at k = 100 the sample costs more than it saves.
+// Sample scans: every 32nd tile, on databases of at least 2 048 tiles (the
+// sample then holds >= 4 096 vectors, eight times the largest k), when a wave
+// scans fewer than 7 k vectors, or fewer than 32 k for k > 128 -- then a large
+// share of all keys would enter some wave's list.  Measured per query: on
+// N = 1e7, d = 1024 (4 883 vectors per wave) k = 512 falls from about 0.95 ms
+// to 0.49 ms and k = 200 is 0.43 ms, while at k = 100 (49 k per wave) the
+// sample would cost 0.03 ms more than it saves; on N = 1e6, d = 768 (488 per
+// wave) k = 100 falls from 0.069 ms to 0.049 ms and k = 128 from 0.077 ms to
+// 0.048 ms, while k = 32 would rise from 0.038 ms to 0.045 ms.
 constexpr int kSampleStride = 32;
-constexpr int kSampleMinK = 128;
 constexpr int64_t kSampleMinTiles = 2048;
+bool use_sample(int64_t per_wave, int k) {
+  return per_wave < 7 * static_cast<int64_t>(k) || (k > 128 && per_wave < 32 * static_cast<int64_t>(k));
+}
 }  // namespace
 
 // Two workgroups of four waves per compute unit keep 16 KiB of loads in flight
@@ -38,11 +45,12 @@ int search_plain(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids,
   const bool sparse = engine == TQ_ENGINE_SPARSE || (engine == TQ_ENGINE_AUTO && tqi::sparse_preferred(db->dev));
   if (sparse && !db->dev.sparse) return fail(TQ_ERR_INVALID, "no index-list copy of this database");
   const int G = grid > 0 ? grid : sparse ? default_sparse_grid(db) : default_plain_grid(db);
-  // Large k: each wave keeps k keys of a few thousand vectors, so many keys
-  // enter some list.  A first scan of every kSampleStride-th tile gives each
-  // query a floor (the sample's k-th key, never above the k-th key overall)
-  // below which the full scan drops keys.
-  const bool sampled = !sparse && k > kSampleMinK && db->dev.ntiles >= kSampleMinTiles;
+  // Large k against the vectors a wave scans: each wave keeps k keys of its
+  // share, so many keys enter some list.  A first scan of every
+  // kSampleStride-th tile gives each query a floor (the sample's k-th key,
+  // never above the k-th key overall) below which the full scan drops keys.
+  const int64_t per_wave = db->dev.ntiles * 64 / (static_cast<int64_t>(G) * 4);
+  const bool sampled = !sparse && db->dev.ntiles >= kSampleMinTiles && use_sample(per_wave, k);
   const size_t per_query = static_cast<size_t>(G) * k * sizeof(uint64_t);
   const size_t per_query_all = per_query + (sampled ? 2 * static_cast<size_t>(k) * sizeof(int32_t) : 0);
   const int chunk = static_cast<int>(std::max<size_t>(1, std::min<size_t>(nq, kPartialBudget / per_query_all)));
