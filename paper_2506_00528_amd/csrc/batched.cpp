@@ -202,7 +202,7 @@ int get_entry(tq_db *db, hipStream_t s, int bucket, int k, const Shape &sh, Batc
   hipError_t err = hipMalloc(&e.qprep, qbytes);
   if (err == hipSuccess) err = hipMalloc(&e.prm, sizeof(tqi::BatchParams));
   if (err == hipSuccess) err = hipMalloc(&e.partial, lists * k * sizeof(uint64_t));
-  if (err == hipSuccess) err = hipMalloc(&e.bound, lists * sizeof(uint64_t));
+  if (err == hipSuccess) err = hipMalloc(&e.bound, lists * tqi::kBoundSlotsPerPart * sizeof(uint64_t));
   if (err == hipSuccess)
     err = hipMalloc(&e.mid, static_cast<size_t>(tqi::merge_batched_mid_keys(bucket, sh.grid + tqi::kXcds, k)) *
                                 sizeof(uint64_t));

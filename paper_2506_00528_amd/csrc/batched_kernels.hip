@@ -50,7 +50,7 @@ __global__ __launch_bounds__(256) void batch_prep_kernel(const uint32_t *__restr
   if (bound) {
     BatchParams b;
     batch_split(b, nq, qtile, grid, 0, ntiles);
-    const int64_t nb = static_cast<int64_t>(nq) * b.parts;
+    const int64_t nb = static_cast<int64_t>(nq) * b.parts * kBoundSlotsPerPart;
     for (int64_t i = g; i < nb; i += static_cast<int64_t>(gridDim.x) * blockDim.x) bound[i] = 0;
   }
   if (g < static_cast<int64_t>(bucket) * W4) {
@@ -113,9 +113,11 @@ __global__ __launch_bounds__(kBatchBlock) void scan_batched_kernel(const uint4 *
                                                                   const BatchParams *__restrict__ prm, int k,
                                                                   uint64_t *__restrict__ partial) {
   __shared__ uint64_t lds[2][kBatchWaves * 64 * R];
+  __shared__ uint64_t lbs[kBatchWaves * QT];  // each query's bound from the other waves and parts
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int nq = prm->nq, nqt = prm->nqt, parts = prm->parts;
+  uint64_t *const lb = lbs + wave * QT;
   const int64_t tpp = prm->tiles_per_part;
   const int64_t tile_lo = prm->tile_lo, tile_hi = prm->tile_hi;
   const int items = nqt * parts;
@@ -136,6 +138,57 @@ __global__ __launch_bounds__(kBatchBlock) void scan_batched_kernel(const uint4 *
       list[qi].clear();
       thr[qi] = 0;
     }
+    if (lane < QT) lb[lane] = 0;
+
+    // Cross-part bound (as in the matrix kernel, with each wave's share of a
+    // part -- tiles t0 + wave + 4 i -- as its own sub-part): with S sub-parts
+    // holding tiles and m = ceil(k / S), every sub-part publishes the m-th key
+    // of its list to its own slot, and the smallest slot of a query (0 while
+    // one is empty) is a lower bound on the query's k-th key overall; keys
+    // not above it are dropped.
+    auto refresh = [&]() {
+      uint64_t *bound = prm->bound;
+      const int peff = static_cast<int>(max<int64_t>(1, min<int64_t>(parts, (tile_hi - tile_lo + tpp - 1) / tpp)));
+      const int nsub = peff * kBatchWaves;
+      const int mth = (k + nsub - 1) / nsub;
+#pragma unroll
+      for (int qi = 0; qi < QT; ++qi) {
+        if (qi < nact) {
+          const uint64_t mk = list[qi].at(mth - 1);
+          if (lane == 0 && mk)
+            __hip_atomic_store(bound + (static_cast<int64_t>(q0 + qi) * parts + part) * kBatchWaves + wave, mk,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+      // lane l reads slots l / QT, l / QT + 64 / QT, ... of query l % QT: the
+      // loads of all queries are in flight together
+      const int rq = lane % QT;
+      uint64_t mn = 0;
+      if (rq < nact) {
+        mn = ~0ull;
+        const uint64_t *slots = bound + static_cast<int64_t>(q0 + rq) * parts * kBatchWaves;
+        for (int p = lane / QT; p < nsub; p += 64 / QT) {
+          const uint64_t v = __hip_atomic_load(slots + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          mn = v < mn ? v : mn;
+        }
+      }
+#pragma unroll
+      for (int off = QT; off < 64; off <<= 1) {
+        const uint64_t o = __shfl_xor(static_cast<unsigned long long>(mn), off);
+        mn = o < mn ? o : mn;
+      }
+#pragma unroll
+      for (int qi = 0; qi < QT; ++qi) {
+        const uint64_t b = readlane64(mn, qi);
+        if (b > thr[qi]) thr[qi] = b;
+      }
+      if (lane < QT) lb[lane] = mn;
+      __builtin_amdgcn_wave_barrier();
+    };
+    // (lists of 256 or 512 keys only: for smaller k the refreshes cost more
+    // than the insertions they save)
+    const bool prune = R >= 4 && prm->bound != nullptr;
+    int next = 1, done = 0;
 
     for (int64_t t = t0 + wave; t < t1; t += kBatchWaves) {
       const uint4 *tp = tiles + t * (2 * NC * 64);
@@ -160,8 +213,12 @@ __global__ __launch_bounds__(kBatchBlock) void scan_batched_kernel(const uint4 *
             delta_word(a, qw[4 * c + 3], qw[4 * NC + 4 * c + 3], vz[c].w, vg[c].w);
           }
           const uint64_t key = make_key(delta_value(a), static_cast<uint32_t>(id));
-          offer_keys<R>(list[qi], thr[qi], key, ok, km1);
+          offer_keys<R>(list[qi], thr[qi], key, ok, km1, prune ? lb[qi] : 0ull);
         }
+      }
+      if (prune && ++done >= next) {
+        refresh();
+        next = next < 64 ? 2 * next : next + 64;
       }
     }
 

@@ -94,7 +94,7 @@ struct tq_server {
   uint64_t *d_running = nullptr; // max_slots x k_run
   uint64_t *d_partial = nullptr; // (qtile * grid + max_slots) x k_run
   uint64_t *d_mid = nullptr;     // first-stage merge results
-  uint64_t *d_bound = nullptr;   // per (query, part) published keys of a matrix tick
+  uint64_t *d_bound = nullptr;   // per (query, part, wave) published keys of a tick
   char *d_tick = nullptr;        // [BatchParams][slots: max_slots ints][retire: max_slots ints]
   tqi::BatchParams *d_prm = nullptr;
   int *d_slots = nullptr;
@@ -210,7 +210,7 @@ hipError_t enqueue_tick(tq_server *s, TickPlan &p, TickStage &st) {
   b.running_stride = s->k_run;
   b.ids = nullptr;
   b.scores = nullptr;
-  b.bound = matrix ? s->d_bound : nullptr;  // (zeroed below, before the scan)
+  b.bound = s->d_bound;  // (zeroed below, before the scan)
   const size_t max_slots = s->slot_used.size();
   std::memcpy(st.host, &b, sizeof b);
   std::memcpy(st.host + sizeof b, p.slots.data(), nq * sizeof(int));
@@ -223,8 +223,8 @@ hipError_t enqueue_tick(tq_server *s, TickPlan &p, TickStage &st) {
   st.used = true;
   // scan the segment for every active query and fold it into the running lists
   e = tqi::gather_rows_launch(s->d_qrows, s->d_slots, nq, 8 * db.nc, s->d_qtick, s->stream);
-  if (e == hipSuccess && matrix)
-    e = tqi::fill_zero_launch(s->d_bound, static_cast<int64_t>(nq) * b.parts, s->stream);
+  if (e == hipSuccess)
+    e = tqi::fill_zero_launch(s->d_bound, static_cast<int64_t>(nq) * b.parts * tqi::kBoundSlotsPerPart, s->stream);
   if (e != hipSuccess) return e;
   {
     TimedLaunch t(kTimeBatched, s->stream);
@@ -456,8 +456,8 @@ int tq_serve_create(const tq_db *db, const tq_serve_cfg *cfg, tq_server **out) {
   // query tiles of up to 64 (matrix engine) or s->qtile (popcount engine)
   dm((void **)&s->d_partial,
      (static_cast<size_t>(std::max(64, s->qtile)) * s->grid + (tqi::kXcds + 1) * M) * s->k_run * sizeof(uint64_t));
-  dm((void **)&s->d_bound,
-     (static_cast<size_t>(std::max(64, s->qtile)) * s->grid + (tqi::kXcds + 1) * M) * sizeof(uint64_t));
+  dm((void **)&s->d_bound, (static_cast<size_t>(std::max(64, s->qtile)) * s->grid + (tqi::kXcds + 1) * M) *
+                               tqi::kBoundSlotsPerPart * sizeof(uint64_t));
   int64_t mid_keys = 0;
   for (int k = 1; k <= s->k_run; ++k)
     mid_keys = std::max(mid_keys, tqi::merge_batched_mid_keys(static_cast<int>(M), s->grid + tqi::kXcds, k));

@@ -25,12 +25,16 @@ struct BatchParams {
   int64_t running_stride;  // keys per running row (>= the call's k)
   int32_t *ids;            // caller's outputs, nq x k (when running is null)
   int32_t *scores;
-  uint64_t *bound;         // optional: nq x parts keys, zero before the scan;
-                           // (query, part) publishes there the m-th key of its
-                           // list, m = ceil(k / parts holding tiles), and the
-                           // scan drops keys below the smallest of a query's
-                           // (see scan_mfma_kernel); null: no such pruning
+  uint64_t *bound;         // optional: nq x parts x kBoundSlotsPerPart keys,
+                           // zero before the scan; the scans publish there the
+                           // m-th keys of their (query, part) or (query, part,
+                           // wave) lists and drop keys below the smallest of a
+                           // query's (see scan_mfma_kernel,
+                           // scan_batched_kernel); null: no such pruning
 };
+// Bound slots per (query, part): the popcount scan's four waves each keep
+// their own lists; the matrix scan uses the first slot block only.
+constexpr int kBoundSlotsPerPart = 4;
 
 // Work items are (query tile, database part) pairs.  The hardware dispatcher
 // places workgroup b on XCD b mod 8, and a persistent workgroup keeps item
@@ -68,8 +72,8 @@ __host__ __device__ inline void batch_split(BatchParams &b, int nq, int qtile, i
 // Largest query tile the batched scan supports for this k.
 int batched_max_qtile(int k);
 
-// `bound` (may be null) holds at least nq * parts keys; the prep kernel zeroes
-// them.
+// `bound` (may be null) holds at least nq * parts * kBoundSlotsPerPart keys;
+// the prep kernel zeroes them.
 hipError_t batch_prep_launch(const uint32_t *qcodes, int nq, int bucket, const DbDev &db, int qtile, int grid,
                              int32_t *ids, int32_t *scores, uint32_t *qprep, BatchParams *prm, uint64_t *bound,
                              hipStream_t s);
