@@ -264,3 +264,28 @@ def test_matrix_cross_part_bound_adversarial(tq, o, qtile, grid):
         ei, es = o.knn(VQ, V, k)
         assert np.array_equal(sc, es) and np.array_equal(ids, ei), k
     db.destroy()
+
+
+@pytest.mark.parametrize("grid", [64, 512])
+def test_popcount_cross_part_bound_adversarial(tq, o, grid):
+    """The popcount engine's bound for k > 128 (each wave's share of a part is
+    a sub-part): planted copies of each query at the lowest ids, in one middle
+    block and at the highest ids, on many sub-parts, with k above and below
+    the number of copies."""
+    rng = np.random.default_rng(57 + grid)
+    d, x, n = 256, 64, 30000
+    V = o.encode(rng.standard_normal((n, d)).astype(np.float32), x)
+    planted = o.encode(rng.standard_normal((4, d)).astype(np.float32), x)
+    for j in range(4):
+        V[j * 10:j * 10 + 10] = planted[j]
+        V[15000 + j * 200:15000 + j * 200 + 200] = planted[j]
+        V[n - 40 + j * 10:n - 40 + j * 10 + 10] = planted[j]
+    VQ = np.concatenate([planted, o.encode(rng.standard_normal((5, d)).astype(np.float32), x)])
+    db = tq.tq_db_create(dev_codes(o.pack(V)), d, x)
+    for k in (129, 200, 512):
+        say(f"popcount bound adversarial grid={grid} k={k}")
+        ids, sc = run(tq, db, o.pack(VQ), k, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_POPCOUNT, qtile=4,
+                      grid=grid)
+        ei, es = o.knn(VQ, V, k)
+        assert np.array_equal(sc, es) and np.array_equal(ids, ei), k
+    db.destroy()
