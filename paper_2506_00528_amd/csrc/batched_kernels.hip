@@ -21,6 +21,7 @@ namespace {
 
 constexpr int kBatchWaves = 4;
 constexpr int kBatchBlock = 64 * kBatchWaves;
+static_assert(kBatchWaves == kBoundSlotsPerPart, "one bound slot per wave of a part");
 
 // Canonical query codes -> nz/ng words padded to 4*nc per plane (the layout
 // the scan reads); rows in [nq, rows) are written as zeros.
@@ -138,7 +139,7 @@ __global__ __launch_bounds__(kBatchBlock) void scan_batched_kernel(const uint4 *
       list[qi].clear();
       thr[qi] = 0;
     }
-    if (lane < QT) lb[lane] = 0;
+    if (R >= 4 && lane < QT) lb[lane] = 0;
 
     // Cross-part bound (as in the matrix kernel, with each wave's share of a
     // part -- tiles t0 + wave + 4 i -- as its own sub-part): with S sub-parts
