@@ -36,7 +36,9 @@ struct Shape {
 };
 
 // ---------------------------------------------------------------------------
-// tuning cache: key "nc<nc>/r<R>/b<bucket>" -> Shape; optional JSON file
+// tuning cache: key "nc<nc>/r<R>/b<bucket>/t<log2 tiles>" -> Shape (the
+// database's size class is part of the key: the best grid and the plain /
+// batched split depend on it); optional JSON file
 // ---------------------------------------------------------------------------
 struct TuneCache {
   std::mutex mu;
@@ -45,9 +47,15 @@ struct TuneCache {
 };
 TuneCache g_tune;
 
-std::string tune_key(int nc, int k, int bucket) {
-  char b[64];
-  std::snprintf(b, sizeof b, "nc%d/r%d/b%d", nc, tqi::rows_for_k(k), bucket);
+int size_class(int64_t ntiles) {
+  int c = 0;
+  while ((int64_t(1) << c) < ntiles) ++c;
+  return c;
+}
+
+std::string tune_key(const tqi::DbDev &db, int k, int bucket) {
+  char b[80];
+  std::snprintf(b, sizeof b, "nc%d/r%d/b%d/t%d", db.nc, tqi::rows_for_k(k), bucket, size_class(db.ntiles));
   return b;
 }
 
@@ -92,19 +100,19 @@ void tune_save_locked() {
   std::rename(tmp.c_str(), f);
 }
 
-bool tune_lookup(int nc, int k, int bucket, Shape *out) {
+bool tune_lookup(const tqi::DbDev &db, int k, int bucket, Shape *out) {
   std::lock_guard<std::mutex> g(g_tune.mu);
   tune_load_locked();
-  auto it = g_tune.map.find(tune_key(nc, k, bucket));
+  auto it = g_tune.map.find(tune_key(db, k, bucket));
   if (it == g_tune.map.end()) return false;
   *out = it->second;
   return true;
 }
 
-void tune_store(int nc, int k, int bucket, const Shape &s) {
+void tune_store(const tqi::DbDev &db, int k, int bucket, const Shape &s) {
   std::lock_guard<std::mutex> g(g_tune.mu);
   tune_load_locked();
-  g_tune.map[tune_key(nc, k, bucket)] = s;
+  g_tune.map[tune_key(db, k, bucket)] = s;
   tune_save_locked();
 }
 
@@ -292,7 +300,7 @@ int run_chunk(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids, in
 // popcount, 64 / 128: matrix).
 Shape shape_for(tq_db *db, int k, int bucket, const tq_search_opts *opts) {
   Shape sh;
-  if (!tune_lookup(db->dev.nc, k, bucket, &sh)) sh = default_shape(db, k, bucket);
+  if (!tune_lookup(db->dev, k, bucket, &sh)) sh = default_shape(db, k, bucket);
   int engine = opts ? opts->engine : TQ_ENGINE_AUTO;
   const int qtile = opts ? opts->qtile : 0;
   if (engine == TQ_ENGINE_AUTO && qtile > 0) engine = qtile >= 64 ? TQ_ENGINE_MATRIX : TQ_ENGINE_POPCOUNT;
@@ -325,7 +333,7 @@ int choose_path(tq_db *db, int requested, int nq, int k) {
   if (requested != TQ_PATH_AUTO) return requested;
   const int bucket = bucket_of(std::min(nq, kMaxBucket));
   Shape sh;
-  if (!tune_lookup(db->dev.nc, k, bucket, &sh)) sh = default_shape(db, k, bucket);
+  if (!tune_lookup(db->dev, k, bucket, &sh)) sh = default_shape(db, k, bucket);
   return sh.plain ? TQ_PATH_PLAIN : TQ_PATH_BATCHED;
 }
 
@@ -478,7 +486,7 @@ int autotune(tq_db *db, int nq_max, const int *ks, int nks, hipStream_t s, int v
           best.grid = d.grid;
           best.engine = d.engine;
         }
-        tune_store(db->dev.nc, k, b, best);
+        tune_store(db->dev, k, b, best);
       }
     }
   }

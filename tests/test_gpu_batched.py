@@ -289,3 +289,22 @@ def test_popcount_cross_part_bound_adversarial(tq, o, grid):
         ei, es = o.knn(VQ, V, k)
         assert np.array_equal(sc, es) and np.array_equal(ids, ei), k
     db.destroy()
+
+
+def test_autotune_cache_file(tq, o, small, tmp_path, monkeypatch):
+    """tq_autotune writes its choices to TQ_TUNE_CACHE, keyed by plane width,
+    list rows, batch-size bucket and the database's size class; searches that
+    use them are still exact."""
+    import json
+    import re
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("TQ_TUNE_CACHE", str(path))
+    say("autotune cache file")
+    tq.tq_autotune(small["db"], 16, [10])
+    data = json.loads(path.read_text())
+    assert data and all(re.fullmatch(r"nc\d+/r\d+/b\d+/t\d+", key) for key in data), list(data)[:4]
+    assert {"qtile", "grid", "plain", "engine"} <= set(next(iter(data.values())))
+    for nq in (1, 9, 16):
+        ids, sc = run(tq, small["db"], small["CQ"][:nq], 10, path=tq.TQ_PATH_AUTO)
+        ei, es = o.knn(small["VQ"][:nq], small["V"], 10)
+        assert np.array_equal(sc, es) and np.array_equal(ids, ei), nq
