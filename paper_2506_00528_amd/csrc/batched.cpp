@@ -173,16 +173,28 @@ struct BatchEntry {
   uint64_t *bound = nullptr;  // per (query, part) published keys (BatchParams::bound)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;  // recorded after the entry's latest use
+  uint64_t last_use = 0;
 };
+
+// Entries kept per database; beyond this the least recently used one is freed
+// (after its latest use has finished), so that many distinct k, buckets or
+// streams do not hold device memory without bound.
+constexpr size_t kMaxEntries = 64;
 
 struct BatchedState {
   hipStream_t capture = nullptr;
+  uint64_t clock = 0;
   std::map<std::tuple<hipStream_t, int, int, int, int, int>, BatchEntry> entries;
 };
 
 namespace {
 
 void free_entry(BatchEntry &e) {
+  if (e.done) {
+    (void)hipEventSynchronize(e.done);
+    (void)hipEventDestroy(e.done);
+  }
   if (e.exec) (void)hipGraphExecDestroy(e.exec);
   if (e.graph) (void)hipGraphDestroy(e.graph);
   if (e.qprep) (void)hipFree(e.qprep);
@@ -202,6 +214,13 @@ int get_entry(tq_db *db, hipStream_t s, int bucket, int k, const Shape &sh, Batc
     *out = &it->second;
     return TQ_OK;
   }
+  if (st.entries.size() >= kMaxEntries) {
+    auto victim = st.entries.begin();
+    for (auto v = st.entries.begin(); v != st.entries.end(); ++v)
+      if (v->second.last_use < victim->second.last_use) victim = v;
+    free_entry(victim->second);  // waits for its latest use
+    st.entries.erase(victim);
+  }
   BatchEntry e;
   const size_t qbytes = static_cast<size_t>(bucket) * 8 * db->dev.nc * sizeof(uint32_t);
   // (query, part) lists: nq * parts <= qtile * grid + nq, plus up to 7 parts
@@ -211,6 +230,7 @@ int get_entry(tq_db *db, hipStream_t s, int bucket, int k, const Shape &sh, Batc
   if (err == hipSuccess) err = hipMalloc(&e.prm, sizeof(tqi::BatchParams));
   if (err == hipSuccess) err = hipMalloc(&e.partial, lists * k * sizeof(uint64_t));
   if (err == hipSuccess) err = hipMalloc(&e.bound, lists * tqi::kBoundSlotsPerPart * sizeof(uint64_t));
+  if (err == hipSuccess) err = hipEventCreateWithFlags(&e.done, hipEventDisableTiming);
   if (err == hipSuccess)
     err = hipMalloc(&e.mid, static_cast<size_t>(tqi::merge_batched_mid_keys(bucket, sh.grid + tqi::kXcds, k)) *
                                 sizeof(uint64_t));
@@ -266,12 +286,25 @@ int ensure_graph(tq_db *db, BatchEntry &e, int bucket, int k, const Shape &sh) {
 }
 
 // One chunk of <= kMaxBucket queries.
+int run_chunk_on(tq_db *db, BatchEntry *e, const uint32_t *qcodes, int nq, int k, int32_t *ids, int32_t *scores,
+                 const Shape &sh, bool use_graph, hipStream_t s);
+
 int run_chunk(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids, int32_t *scores, const Shape &sh,
               bool use_graph, hipStream_t s) {
-  const int bucket = bucket_of(nq);
   BatchEntry *e = nullptr;
-  int rc = get_entry(db, s, bucket, k, sh, &e);
+  int rc = get_entry(db, s, bucket_of(nq), k, sh, &e);
   if (rc) return rc;
+  rc = run_chunk_on(db, e, qcodes, nq, k, ids, scores, sh, use_graph, s);
+  // the entry's latest use, for a later eviction
+  e->last_use = ++db->batched->clock;
+  if (hipEventRecord(e->done, s) != hipSuccess && rc == TQ_OK) rc = fail(TQ_ERR_DEVICE, "hipEventRecord");
+  return rc;
+}
+
+int run_chunk_on(tq_db *db, BatchEntry *e, const uint32_t *qcodes, int nq, int k, int32_t *ids, int32_t *scores,
+                 const Shape &sh, bool use_graph, hipStream_t s) {
+  const int bucket = bucket_of(nq);
+  int rc = TQ_OK;
   hipError_t err = tqi::batch_prep_launch(qcodes, nq, bucket, db->dev, sh.qtile, sh.grid, ids, scores, e->qprep,
                                           e->prm, e->bound, s);
   if (err != hipSuccess) return hip_fail(err, "batch prep launch");

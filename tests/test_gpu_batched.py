@@ -308,3 +308,15 @@ def test_autotune_cache_file(tq, o, small, tmp_path, monkeypatch):
         ids, sc = run(tq, small["db"], small["CQ"][:nq], 10, path=tq.TQ_PATH_AUTO)
         ei, es = o.knn(small["VQ"][:nq], small["V"], 10)
         assert np.array_equal(sc, es) and np.array_equal(ids, ei), nq
+
+
+def test_many_distinct_k_evicts_entries(tq, o, small):
+    """Every distinct (bucket, k, shape) keeps buffers and a graph; beyond 64
+    the least recently used is freed after its latest use.  80 values of k in
+    a row, each checked, then the first ones again."""
+    say("batched: 80 distinct k values")
+    CQ, VQ = small["CQ"][:3], small["VQ"][:3]
+    for k in list(range(1, 81)) + [1, 2, 3]:
+        ids, sc = run(tq, small["db"], CQ, k, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_POPCOUNT)
+        ei, es = o.knn(VQ, small["V"], k)
+        assert np.array_equal(sc, es) and np.array_equal(ids, ei), k
