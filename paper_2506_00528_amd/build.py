@@ -1,6 +1,6 @@
 """Build the HIP library libtq.so for gfx950 (MI355X) in-tree.
 
-    python -m paper_2506_00528_amd.build      (or __graft_entry__.build())
+    python -m paper_2506_00528_amd.build
 
 Every source in csrc/ is compiled by hipcc into _build/ and linked into
 paper_2506_00528_amd/libtq.so, which the Python binding loads.

@@ -6,8 +6,8 @@ Functions keep the C names (``tq_encode``, ``tq_db_create``, ``tq_search_knn``,
 pointers; ``stream`` defaults to torch's current stream on the tensor's device.
 Code tensors are ``torch.int32`` holding the canonical uint32 bit patterns.
 
-The library must have been built (``__graft_entry__.build()`` or
-``python -m paper_2506_00528_amd.build``); there is no fallback.
+The library must have been built (``python -m paper_2506_00528_amd.build``);
+there is no fallback.
 """
 from __future__ import annotations
 
@@ -83,7 +83,7 @@ def lib(path: Optional[str] = None):
         return _lib
     p = path or LIB_PATH
     if not os.path.exists(p):
-        raise RuntimeError(f"HIP library {p} is not built; run __graft_entry__.build() first")
+        raise RuntimeError(f"HIP library {p} is not built; run python -m paper_2506_00528_amd.build first")
     L = ctypes.CDLL(p)
     vp, i32, i64, u64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t
     P = ctypes.POINTER
