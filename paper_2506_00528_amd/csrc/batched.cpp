@@ -128,15 +128,16 @@ int default_engine(int k, int nq) {
 
 namespace {
 
-// Workgroups of the matrix engine that fit on one CU at once: two of four
-// waves for 64-query tiles and for 128-query tiles at k <= 16; one for the
-// eight-wave 128-query tiles of k > 16 and for 256-query tiles.
+// Workgroups per CU of the matrix engine's default grid: two for 64-query
+// tiles (four waves) and for the eight-wave 128-query tiles of k <= 16 (142
+// VGPRs; measured best at two per CU), one for the eight-wave 128-query tiles
+// of k > 16 and for 256-query tiles.
 int mfma_resident_per_cu(int k, int qtile) {
   return (qtile == 256 || (qtile == 128 && k > tqi::kGroupMaxK)) ? 1 : 2;
 }
 
 int default_matrix_qtile(int k, int bucket) {
-  if (k <= tqi::kGroupMaxK) return bucket >= 256 ? 256 : bucket >= 128 ? 128 : 64;
+  if (k <= tqi::kGroupMaxK) return bucket >= 512 ? 256 : bucket >= 128 ? 128 : 64;
   return bucket >= 256 ? 128 : 64;
 }
 
@@ -147,9 +148,9 @@ Shape default_shape(const tq_db *db, int k, int bucket) {
   s.plain = bucket == 1;
   s.engine = default_engine(k, bucket);
   if (s.engine == TQ_ENGINE_MATRIX) {
-    // the largest tile a bucket fills (N = 1e7, d = 1024, 1 024 queries:
-    // k = 10 5.2 / 6.1 / 7.5 ms on 256 / 128 / 64-query tiles; k = 100 9.6 ms
-    // vs 10.5 ms on 128 / 64), for k > 16 from 256 queries
+    // (N = 1e7, d = 1024, k = 10: 1 024 queries 5.2 / 5.3 / 7.4 ms on 256 /
+    // 128 / 64-query tiles, 256 queries 1.8 / 1.6 / 2.2 ms; k = 100, 1 024
+    // queries: 9.6 ms vs 10.5 ms on 128 / 64)
     s.qtile = default_matrix_qtile(k, bucket);
     s.grid = cu * mfma_resident_per_cu(k, s.qtile);
   } else {

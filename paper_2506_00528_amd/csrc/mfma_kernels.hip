@@ -342,10 +342,10 @@ __global__ __launch_bounds__(64 * WV, R * RB * WV <= 8 ? 8 / WV : 1) void scan_m
 // lives in exactly those lanes -- entry l % 16 of the list of row
 // 4 (l / 16) + i sits in register i of lane l -- so a list costs a quarter of a
 // register pair, the four groups insert their own candidates at the same
-// time, and a wave holds 16 RB queries: 64- and 128-query tiles are four
-// waves with RB = 1 or 2, 256-query tiles eight waves with RB = 2 (twice the
-// operand reuse of a 64-query tile in every wave, and half the staging work
-// per thread).
+// time, and a wave holds 16 RB queries: 64-query tiles are four waves with
+// RB = 1, 128-query tiles eight waves with RB = 1 (half the staging work per
+// thread), 256-query tiles eight waves with RB = 2 (twice the operand reuse in
+// every wave as well).
 
 // 16 keys per group, descending; empty entries are 0.
 struct GroupList {
@@ -534,7 +534,7 @@ hipError_t scan_mfma_launch_nc(const DbDev &db, const uint32_t *qprep, const Bat
                                int grid, uint64_t *partial, hipStream_t s) {
   if (k <= kGroupMaxK) {
     if (qtile == 64) return launch_g<NC, 1>(db, qprep, prm, k, grid, partial, s);
-    if (qtile == 128) return launch_g<NC, 2>(db, qprep, prm, k, grid, partial, s);
+    if (qtile == 128) return launch_g<NC, 1, 8>(db, qprep, prm, k, grid, partial, s);  // eight waves of 16
     return launch_g<NC, 2, 8>(db, qprep, prm, k, grid, partial, s);  // 256: eight waves of 32
   }
   const int r = rows_for_k(k);
