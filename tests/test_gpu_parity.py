@@ -107,7 +107,7 @@ def test_encode_rows_of_many_lengths(tq, o):
         assert np.array_equal(gpu_codes(tq, X, 67), oracle_codes(o, X, 67))
 
 
-@pytest.mark.parametrize("d", [96, 384, 1024])
+@pytest.mark.parametrize("d", [96, 384, 512, 768, 1024])
 def test_encode_many_rows_per_wave(tq, o, d):
     """Enough rows that every wave encodes several in turn, so each search
     starts from the previous row's threshold: rows of one scale (a good guess),
