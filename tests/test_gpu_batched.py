@@ -150,12 +150,13 @@ def test_autotune_then_auto(tq, o, small, tmp_path, monkeypatch):
 # the matrix-core engine (fp4 MFMA): same results, bit for bit
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("k", [1, 10, 16, 17, 64, 65, 100, 128])
-@pytest.mark.parametrize("nq", [1, 3, 17, 100, 300])
-@pytest.mark.parametrize("qtile", [64, 128, 256])
+# 256-query tiles serve k <= 16 only (the others are rejected: see the argument checks)
+MATRIX_CASES = [(qtile, nq, k) for qtile in (64, 128, 256) for nq in (1, 3, 17, 100, 300)
+                for k in (1, 10, 16, 17, 64, 65, 100, 128) if qtile < 256 or k <= 16]
+
+
+@pytest.mark.parametrize("qtile,nq,k", MATRIX_CASES)
 def test_matrix_vs_oracle(tq, o, small, k, nq, qtile):
-    if qtile == 256 and k > 16:
-        pytest.skip("256-query tiles serve k <= 16")
     say(f"matrix engine small k={k} nq={nq} qtile={qtile}")
     ids, sc = run(tq, small["db"], small["CQ"][:nq], k, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_MATRIX,
                   qtile=qtile)

@@ -46,12 +46,12 @@ def search(tq, db, CQ, k, **kw):
     return ids.cpu().numpy(), sc.cpu().numpy()
 
 
-@pytest.mark.parametrize("n,d,x", [(1, 8, 1), (63, 64, 8), (65, 100, 12), (1000, 384, 7), (4097, 384, 24),
-                                   (10000, 384, 48), (3001, 768, 96), (2500, 1024, 128), (777, 1000, 3)])
-@pytest.mark.parametrize("k", [1, 10, 100, 512])
+SPARSE_SHAPES = [(1, 8, 1), (63, 64, 8), (65, 100, 12), (1000, 384, 7), (4097, 384, 24), (10000, 384, 48),
+                 (3001, 768, 96), (2500, 1024, 128), (777, 1000, 3)]
+
+
+@pytest.mark.parametrize("n,d,x,k", [(n, d, x, k) for (n, d, x) in SPARSE_SHAPES for k in (1, 10, 100, 512) if k <= n])
 def test_sparse_vs_oracle(tq, o, n, d, x, k):
-    if k > n:
-        pytest.skip("k > n")
     rng = np.random.default_rng(n * 7 + d * 3 + x)
     V, VQ = make(o, rng, n, d, x, 13)
     say(f"sparse n={n} d={d} x={x} k={k}")
