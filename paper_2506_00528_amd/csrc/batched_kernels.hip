@@ -165,14 +165,8 @@ __global__ __launch_bounds__(kBatchBlock) void scan_batched_kernel(const uint4 *
       // loads of all queries are in flight together
       const int rq = lane % QT;
       uint64_t mn = 0;
-      if (rq < nact) {
-        mn = ~0ull;
-        const uint64_t *slots = bound + static_cast<int64_t>(q0 + rq) * parts * kBatchWaves;
-        for (int p = lane / QT; p < nsub; p += 64 / QT) {
-          const uint64_t v = __hip_atomic_load(slots + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          mn = v < mn ? v : mn;
-        }
-      }
+      if (rq < nact)
+        mn = min_published_keys(bound + static_cast<int64_t>(q0 + rq) * parts * kBatchWaves, lane / QT, nsub, 64 / QT);
 #pragma unroll
       for (int off = QT; off < 64; off <<= 1) {
         const uint64_t o = __shfl_xor(static_cast<unsigned long long>(mn), off);

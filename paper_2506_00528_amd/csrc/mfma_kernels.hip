@@ -73,11 +73,8 @@ __device__ __forceinline__ float row_threshold(uint64_t own, uint64_t lb) {
   return lb > own ? static_cast<float>(key_score(lb)) - 0.5f : score_of(own);
 }
 
-// Relaxed loads and stores at device scope: the published keys of other
-// workgroups (on other XCDs) are read around the non-coherent L2s.
-__device__ __forceinline__ uint64_t load_shared_key(const uint64_t *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+// Relaxed stores at device scope: the published keys are read by workgroups
+// on other XCDs, around the non-coherent L2s (min_published_keys).
 __device__ __forceinline__ void store_shared_key(uint64_t *p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -284,14 +281,9 @@ __global__ __launch_bounds__(64 * WV, R * RB * WV <= 8 ? 8 / WV : 1) void scan_m
       }
       const int rq = lane / kLanesPerQuery;
       uint64_t mn = 0;
-      if (rq < nact) {
-        mn = ~0ull;
-        const uint64_t *row = bound + static_cast<int64_t>(q0 + rq) * parts;
-        for (int p = lane % kLanesPerQuery; p < peff; p += kLanesPerQuery) {
-          const uint64_t v = load_shared_key(row + p);
-          mn = v < mn ? v : mn;
-        }
-      }
+      if (rq < nact)
+        mn = min_published_keys(bound + static_cast<int64_t>(q0 + rq) * parts, lane % kLanesPerQuery, peff,
+                                kLanesPerQuery);
 #pragma unroll
       for (int off = 1; off < kLanesPerQuery; off <<= 1) {
         const uint64_t o = __shfl_xor(static_cast<unsigned long long>(mn), off);

@@ -197,6 +197,29 @@ __device__ __forceinline__ void offer_keys(WaveList<R> &list, uint64_t &thr, uin
   }
 }
 
+// Smallest of the keys p[first], p[first + step], ... below p[end], read with
+// relaxed device-scope loads (keys other workgroups publish); ~0 if there are
+// none.  Eight loads are issued before the first is waited for: one at a time,
+// each would cost a full round trip to the device-coherent level.  The last
+// group re-reads p[first] in place of the indices past `end`, which cannot
+// change a minimum.
+__device__ __forceinline__ uint64_t min_published_keys(const uint64_t *p, int first, int end, int step) {
+  uint64_t mn = ~0ull;
+  if (first >= end) return mn;
+  constexpr int kInFlight = 8;
+  for (int i0 = first; i0 < end; i0 += kInFlight * step) {
+    uint64_t v[kInFlight];
+#pragma unroll
+    for (int b = 0; b < kInFlight; ++b) {
+      const int i = i0 + b * step;
+      v[b] = __hip_atomic_load(p + (i < end ? i : first), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+#pragma unroll
+    for (int b = 0; b < kInFlight; ++b) mn = v[b] < mn ? v[b] : mn;
+  }
+  return mn;
+}
+
 // ---------------------------------------------------------------------------
 // Workgroup-wide merge of sorted lists in LDS
 // ---------------------------------------------------------------------------
