@@ -129,7 +129,7 @@ int default_engine(int k, int nq) {
 namespace {
 
 // Workgroups per CU of the matrix engine's default grid: two for 64-query
-// tiles (four waves) and for the eight-wave 128-query tiles of k <= 16 (142
+// tiles (four waves) and for the eight-wave 128-query tiles of k <= 16 (124
 // VGPRs; measured best at two per CU), one for the eight-wave 128-query tiles
 // of k > 16 and for 256-query tiles.
 int mfma_resident_per_cu(int k, int qtile) {

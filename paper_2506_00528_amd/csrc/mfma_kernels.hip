@@ -18,8 +18,9 @@
 // 4s + l / 16 of K-step s (128 coordinates, one 16-byte chunk of a plane).
 //
 // Work: a persistent grid walks (query tile, database part) items like the
-// popcount kernel, but here a workgroup's four waves each own 16*RB queries
-// of the tile (64*RB per tile) and all four sweep the same database tiles.
+// popcount kernel, but here each of a workgroup's WV waves (four or eight)
+// owns 16*RB queries of the tile (16*RB*WV per tile) and all of them sweep
+// the same database tiles.
 // Each 64-vector tile is read from HBM once per workgroup, re-coded to fp4
 // operands by the whole workgroup while it is staged into LDS (double
 // buffered: the next tile's loads are in flight while the current one is
@@ -39,8 +40,7 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v8i __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int kMfmaWaves = 4;
-constexpr int kMfmaBlock = 64 * kMfmaWaves;
+constexpr int kMfmaWaves = 4;  // waves per workgroup unless a tile says otherwise
 constexpr int kScaleOne = 0x7f7f7f7f;  // e8m0 exponent 127 in every byte: scale 2^0
 
 // 32 coordinates (one word of each plane) -> 32 fp4 operand values (16 bytes).
