@@ -570,8 +570,9 @@ def main():
         "rerank": rerank,
         "masked": masked,
         "sparse": sparse,
-        "encode": {"rows_per_s": round(enc_bytes / (4 * (d + 2 * W)) / (enc_ms * 1e-3), 1),
-                   "gbps": round(enc_bytes / (enc_ms * 1e-3) / 1e9, 1)},
+        "encode": {"kernel": "encode_kernel", "bound": "hbm", "rows_per_s": round(enc_bytes / (4 * (d + 2 * W)) / (enc_ms * 1e-3), 1),
+                   "gbps": round(enc_bytes / (enc_ms * 1e-3) / 1e9, 1),
+                   "frac": round(enc_bytes / (enc_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)},
         "roofline": {"kernel": "scan_plain_kernel", "bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": traffic, "bytes_per_launch": db_bytes,
