@@ -126,6 +126,27 @@ def test_encode_many_rows_per_wave(tq, o, d):
         assert np.array_equal(gpu_codes(tq, X, x), oracle_codes(o, X, x)), f"d={d} x={x}"
 
 
+@pytest.mark.parametrize("d", [100, 768, 1024])
+def test_encode_outlier_rows(tq, o, d):
+    """Rows with one huge coordinate next to ordinary rows: a wave's first-row
+    guess (a quarter of the largest magnitude) and the guess carried from the
+    previous row are far from the threshold, above and below, so the search
+    gallops over many binades before it brackets the cut."""
+    rng = np.random.default_rng(3000 + d)
+    n = 20000
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    kind = rng.integers(0, 3, size=n)  # 0 ordinary, 1 one coordinate 1e30, 2 scaled to 1e-30 with one 1.0
+    X[kind == 2] *= np.float32(1e-30)
+    rows = np.nonzero(kind > 0)[0]
+    cols = rng.integers(0, d, size=rows.size)
+    sign = np.where(rng.integers(0, 2, size=rows.size) == 0, 1.0, -1.0)
+    X[rows, cols] = (sign * np.where(kind[rows] == 1, 1e30, 1.0)).astype(np.float32)
+    assert np.isfinite(X).all()
+    for x in sorted({1, 2, d // 4, oracle.default_x(d)}):
+        say(f"encode outlier rows n={n} d={d} x={x}")
+        assert np.array_equal(gpu_codes(tq, X, x), oracle_codes(o, X, x)), f"d={d} x={x}"
+
+
 def test_encode_nonfinite_sets_flag(tq, o):
     rng = np.random.default_rng(7)
     X = rng.standard_normal((6, 64)).astype(np.float32)
