@@ -40,12 +40,13 @@ def compare(gi, gs, ei, es, scale):
     fin = ~np.isneginf(es)
     assert np.all(np.abs(gs[fin] - es[fin]) <= TOL * scale), np.max(np.abs(gs[fin] - es[fin]))
     assert np.array_equal(gi[~fin], ei[~fin])
+    k = ei.shape[1]
     for q in range(ei.shape[0]):
+        kf = int(np.sum(fin[q]))  # the empty (-inf) slots follow and are checked above
         j = 0
-        k = ei.shape[1]
-        while j < k:  # runs of oracle scores within the tolerance of each other
+        while j < kf:  # runs of oracle scores within the tolerance of each other
             e = j + 1
-            while e < k and es[q, e - 1] - es[q, e] <= 2 * TOL * scale:
+            while e < kf and es[q, e - 1] - es[q, e] <= 2 * TOL * scale:
                 e += 1
             if e - j == 1:
                 assert gi[q, j] == ei[q, j], (q, j)
