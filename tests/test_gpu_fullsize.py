@@ -10,7 +10,8 @@ test's time, so codes are compared on sampled chunks, and each sampled
 query's top-10 is checked by properties that hold at any size: every returned
 score equals the oracle's Delta for that (query, row); results are ordered
 (Delta desc, id asc); and no row of the sampled chunks that is not in the
-result beats the k-th result.  Plain and batched results must be identical.
+result beats the k-th result.  Plain and batched results must be identical,
+also for batches of 40 to 600 queries at k = 1, 10 and 100.
 """
 import sys
 
@@ -130,4 +131,15 @@ def test_large_sampled(tq, o):
                 rid = r0 + int(i)
                 if rid not in chosen:
                     assert key_of(Ds[i], rid) < kth, f"row {rid} beats the k-th result of query {q}"
+    # the batched path at the batching workload's batch sizes and k (matrix
+    # engine: 256-query tiles for k <= 16, 128- and 64-query tiles for k = 100)
+    # gives the same bits as the plain path
+    Q2 = datagen.rows(w["spec"], datagen.QUERIES, 100, 600, dev)
+    qc2 = tq.tq_encode(Q2, x)
+    for nq, kk in ((600, 1), (600, 10), (300, 100), (40, 100)):
+        say(f"large full size: batched vs plain nq={nq} k={kk}")
+        ib2, sb2 = tq.tq_search_knn(db, qc2[:nq], kk, path=tq.TQ_PATH_BATCHED)
+        ip2, sp2 = tq.tq_search_knn(db, qc2[:nq], kk, path=tq.TQ_PATH_PLAIN)
+        torch.cuda.synchronize()
+        assert torch.equal(ib2, ip2) and torch.equal(sb2, sp2), (nq, kk)
     db.destroy()
