@@ -12,6 +12,9 @@ score equals the oracle's Delta for that (query, row); results are ordered
 (Delta desc, id asc); and no row of the sampled chunks that is not in the
 result beats the k-th result.  Plain and batched results must be identical,
 also for batches of 40 to 600 queries at k = 1, 10 and 100.
+
+serving (N = 5e6, d = 768, x = 192): a mix of requests served concurrently
+gives the plain path's rows.
 """
 import sys
 
@@ -142,4 +145,61 @@ def test_large_sampled(tq, o):
         ip2, sp2 = tq.tq_search_knn(db, qc2[:nq], kk, path=tq.TQ_PATH_PLAIN)
         torch.cuda.synchronize()
         assert torch.equal(ib2, ip2) and torch.equal(sb2, sp2), (nq, kk)
+    db.destroy()
+
+
+def test_serving_full_size_mix_equals_plain(tq):
+    """The serving workload's database (N = 5e6, d = 768, x = 192): requests of
+    geometric size (mean 16, at most 256) with k in {10, 100}, submitted from
+    four threads at once, each get exactly the plain path's rows."""
+    import threading
+
+    w = datagen.WORKLOADS["serving"]
+    n, d, x = w["n"], w["d"], w["x"]
+    dev = torch.device("cuda", 0)
+    W = tq.tq_code_words(d)
+    say(f"serving full size: generate + encode N={n} d={d} x={x}")
+    codes = torch.empty((n, 2 * W), dtype=torch.int32, device=dev)
+    for r0, Xc in datagen.iter_rows(w["spec"], datagen.DB, 0, n, dev):
+        tq.tq_encode(Xc, x, codes[r0:r0 + Xc.shape[0]])
+    nq_pool = 512
+    qc = tq.tq_encode(datagen.rows(w["spec"], datagen.QUERIES, 0, nq_pool, dev), x)
+    tq.tq_sync()
+    db = tq.tq_db_create(codes, d, x)
+    del codes
+    say("serving full size: plain-path reference at k = 10 and 100")
+    ref = {}
+    for k in (10, 100):
+        i, s = tq.tq_search_knn(db, qc, k, path=tq.TQ_PATH_PLAIN)
+        torch.cuda.synchronize()
+        ref[k] = (i.cpu().numpy(), s.cpu().numpy())
+    qhost = qc.cpu().numpy().view(np.uint32)
+    rng = np.random.default_rng(11)
+    reqs = []
+    for _ in range(48):
+        while True:
+            nq = int(rng.geometric(1 / 16))
+            if nq <= 256:
+                break
+        reqs.append((int(rng.integers(0, nq_pool - nq + 1)), nq, int(rng.choice([10, 100]))))
+    say(f"serving full size: {len(reqs)} requests from 4 threads")
+    srv = tq.tq_server(db, max_k=100, budget_bytes=1 << 30)
+    tickets = [None] * len(reqs)
+
+    def submitter(part):
+        for i in range(part, len(reqs), 4):
+            q0, nq, k = reqs[i]
+            tickets[i] = srv.submit(qhost[q0:q0 + nq], k)
+
+    th = [threading.Thread(target=submitter, args=(p,)) for p in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    res = [srv.wait(t, 60000) for t in tickets]
+    srv.destroy()
+    for (q0, nq, k), r in zip(reqs, res):
+        ei, es = ref[k]
+        assert r is not None, (q0, nq, k)
+        assert np.array_equal(r[0], ei[q0:q0 + nq]) and np.array_equal(r[1], es[q0:q0 + nq]), (q0, nq, k)
     db.destroy()
