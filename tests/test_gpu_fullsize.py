@@ -11,7 +11,8 @@ query's top-10 is checked by properties that hold at any size: every returned
 score equals the oracle's Delta for that (query, row); results are ordered
 (Delta desc, id asc); and no row of the sampled chunks that is not in the
 result beats the k-th result.  Plain and batched results must be identical,
-also for batches of 40 to 600 queries at k = 1, 10 and 100.
+also for batches of 40 to 600 queries at k = 1, 10 and 100, and the
+index-list engine on the same rows at x = d / 32 equals the bit-plane scan.
 
 serving (N = 5e6, d = 768, x = 192): a mix of requests served concurrently
 gives the plain path's rows.
@@ -88,9 +89,12 @@ def test_large_sampled(tq, o):
     sample_chunks = [0, 47, 101, nchunks - 1]
     say(f"large full size: generate + encode N={n} d={d} x={x}")
     codes = torch.empty((n, 2 * W), dtype=torch.int32, device=dev)
+    xs = d // 32  # the same rows at a small x, for the index-list engine
+    codes_s = torch.empty((n, 2 * W), dtype=torch.int32, device=dev)
     sampled = {}
     for r0, Xc in datagen.iter_rows(w["spec"], datagen.DB, 0, n, dev):
         tq.tq_encode(Xc, x, codes[r0:r0 + Xc.shape[0]])
+        tq.tq_encode(Xc, xs, codes_s[r0:r0 + Xc.shape[0]])
         if r0 // datagen.CHUNK in sample_chunks:
             sampled[r0] = Xc.cpu().numpy()
     Q = datagen.rows(w["spec"], datagen.QUERIES, 0, 4, dev)
@@ -146,6 +150,18 @@ def test_large_sampled(tq, o):
         torch.cuda.synchronize()
         assert torch.equal(ib2, ip2) and torch.equal(sb2, sp2), (nq, kk)
     db.destroy()
+    # the index-list engine on the x = d / 32 codes of the same rows gives the
+    # bit-plane scan's results
+    db_s = tq.tq_db_create(codes_s, d, xs)
+    del codes_s
+    qs = tq.tq_encode(Q2[:16], xs)
+    for kk in (10, 100):
+        say(f"large full size: index lists vs bit planes x={xs} k={kk}")
+        i_s, s_s = tq.tq_search_knn(db_s, qs, kk, path=tq.TQ_PATH_PLAIN, engine=tq.TQ_ENGINE_SPARSE)
+        i_b, s_b = tq.tq_search_knn(db_s, qs, kk, path=tq.TQ_PATH_PLAIN, engine=tq.TQ_ENGINE_POPCOUNT)
+        torch.cuda.synchronize()
+        assert torch.equal(i_s, i_b) and torch.equal(s_s, s_b), kk
+    db_s.destroy()
 
 
 def test_serving_full_size_mix_equals_plain(tq):
