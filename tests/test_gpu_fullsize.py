@@ -12,7 +12,9 @@ score equals the oracle's Delta for that (query, row); results are ordered
 (Delta desc, id asc); and no row of the sampled chunks that is not in the
 result beats the k-th result.  Plain and batched results must be identical,
 also for batches of 40 to 600 queries at k = 1, 10 and 100, and the
-index-list engine on the same rows at x = d / 32 equals the bit-plane scan.
+index-list engine on the same rows at x = d / 32 equals the bit-plane scan;
+masked addition of the float queries is checked by the same kind of
+properties.
 
 serving (N = 5e6, d = 768, x = 192): a mix of requests served concurrently
 gives the plain path's rows.
@@ -149,6 +151,37 @@ def test_large_sampled(tq, o):
         ip2, sp2 = tq.tq_search_knn(db, qc2[:nq], kk, path=tq.TQ_PATH_PLAIN)
         torch.cuda.synchronize()
         assert torch.equal(ib2, ip2) and torch.equal(sb2, sp2), (nq, kk)
+    # masked addition of the float queries, checked by properties: every
+    # returned score is the float rounding of the scalar product with the row's
+    # ternary code (one unit in the last place: both sides sum in double, in
+    # different orders), the order is (score desc, id asc), and no row of the
+    # sampled chunks left out beats the k-th by more than that unit
+    say("large full size: masked addition top-10")
+    mi, ms = tq.tq_search_masked(db, Q, k)
+    torch.cuda.synchronize()
+    mi, ms = mi.cpu().numpy(), ms.cpu().numpy()
+    Qh = Q.cpu().numpy().astype(np.float64)
+    mneed = sorted(set(mi.ravel().tolist()))
+    mrows = torch.empty((len(mneed), d), dtype=torch.float32)
+    for j, r in enumerate(mneed):
+        c = r // datagen.CHUNK
+        blk = datagen.chunk(datagen.SPECS[w["spec"]], datagen.DB, c, dev)
+        mrows[j] = blk[r - c * datagen.CHUNK].cpu()
+    MV = o.encode(mrows.numpy(), x).astype(np.float64)
+    mpos = {r: j for j, r in enumerate(mneed)}
+    ulp = lambda f: float(np.spacing(np.float32(abs(f))))
+    for q in range(4):
+        for j in range(k):
+            f = float(np.float32(Qh[q] @ MV[mpos[mi[q, j]]]))
+            assert abs(float(ms[q, j]) - f) <= ulp(f), (q, j)
+            if j:
+                assert ms[q, j - 1] > ms[q, j] or (ms[q, j - 1] == ms[q, j] and mi[q, j - 1] < mi[q, j]), (q, j)
+        lim = float(ms[q, -1]) + ulp(ms[q, -1])
+        chosen = set(mi[q].tolist())
+        for r0, V in oracle_rows.items():
+            sc = (Qh[q] @ V.astype(np.float64).T).astype(np.float32)
+            for i in np.nonzero(sc > lim)[0]:
+                assert r0 + int(i) in chosen, f"row {r0 + int(i)} beats the masked k-th of query {q}"
     db.destroy()
     # the index-list engine on the x = d / 32 codes of the same rows gives the
     # bit-plane scan's results
