@@ -20,7 +20,8 @@
 // workgroup, and the per-query merge.  Keys order floats exactly: the score's
 // bit pattern is mapped to an unsigned value with the same order (zeros of
 // both signs map to one value) and takes the place of Delta + 2^31 in the
-// 64-bit key.
+// 64-bit key.  Each chunk's registers take the same chunk of the wave's next
+// tile once scored, so loads overlap the table reads at no register cost.
 #include "tq_batched.h"
 #include "tq_device.h"
 
@@ -65,14 +66,21 @@ __global__ __launch_bounds__(kMaskedBlock) void scan_masked_kernel(const uint4 *
   uint64_t thr = 0;
   const int km1 = k - 1;
 
-  for (int64_t t = static_cast<int64_t>(blockIdx.x) * kMaskedWaves + wave; t < ntiles; t += nwaves) {
-    const uint4 *tile = tiles + t * (2 * NC * 64);
-    u32x4 vz[NC], vg[NC];
+  // A chunk's registers take the same chunk of the wave's next tile as soon
+  // as it has been scored, so the next tile's loads overlap this tile's table
+  // reads without a second set of registers (the last tile re-reads itself).
+  const int64_t t_first = static_cast<int64_t>(blockIdx.x) * kMaskedWaves + wave;
+  u32x4 vz[NC], vg[NC];
+  if (t_first < ntiles) {
+    const uint4 *tile = tiles + t_first * (2 * NC * 64);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       vz[c] = load_stream(tile + c * 64 + lane);
       vg[c] = load_stream(tile + (NC + c) * 64 + lane);
     }
+  }
+  for (int64_t t = t_first; t < ntiles; t += nwaves) {
+    const uint4 *next = tiles + (t + nwaves < ntiles ? t + nwaves : t) * (2 * NC * 64);
     double sp[2] = {0.0, 0.0}, sm[2] = {0.0, 0.0};
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -86,6 +94,8 @@ __global__ __launch_bounds__(kMaskedBlock) void scan_masked_kernel(const uint4 *
           sm[nib & 1] += row[nib * 16 + ((g >> (4 * nib)) & 15)];
         }
       }
+      vz[c] = load_stream(next + c * 64 + lane);
+      vg[c] = load_stream(next + (NC + c) * 64 + lane);
     }
     const float score = static_cast<float>((sp[0] + sp[1]) - 2.0 * (sm[0] + sm[1]));
     const int64_t id = t * 64 + lane;
