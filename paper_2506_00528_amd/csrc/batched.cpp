@@ -118,11 +118,14 @@ void tune_store(const tqi::DbDev &db, int k, int bucket, const Shape &s) {
 
 }  // namespace
 
-// Untuned choice, from measurements on MI355X (N = 1e7, d = 1024): the
-// matrix engine wins from 16 queries for k <= 128; the popcount engine below
-// that and for larger k.
+// Untuned choice, from measurements on MI355X: the matrix engine wins from
+// about 10 queries for k <= 128 (N = 1e7, d = 1024, k = 10: 0.58 against
+// 0.71 ms at 10 queries, 0.56 against 0.57 at 8; N = 5e6, d = 768: 0.36
+// against 0.42 ms at 12, 0.33 against 0.30 at 8); the popcount engine below
+// that and for larger k.  (The batched path passes its power-of-two bucket,
+// serving ticks their query count.)
 int default_engine(int k, int nq) {
-  if (tqi::rows_for_k(k) <= 2 && nq >= 16) return TQ_ENGINE_MATRIX;
+  if (tqi::rows_for_k(k) <= 2 && nq >= 10) return TQ_ENGINE_MATRIX;
   return TQ_ENGINE_POPCOUNT;
 }
 
