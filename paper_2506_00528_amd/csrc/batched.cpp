@@ -36,9 +36,12 @@ struct Shape {
 };
 
 // ---------------------------------------------------------------------------
-// tuning cache: key "nc<nc>/r<R>/b<bucket>/t<log2 tiles>" -> Shape (the
-// database's size class is part of the key: the best grid and the plain /
-// batched split depend on it); optional JSON file
+// tuning cache: key "nc<nc>/kc<k class>/b<bucket>/t<log2 tiles>" -> Shape
+// (the database's size class is part of the key: the best grid and the
+// plain / batched split depend on it); optional JSON file.  The k class
+// separates every set of k that has its own kernels and valid query tiles:
+// k <= kGroupMaxK (the matrix engine's grouped lists, 256-query tiles), then
+// one class per list depth R = rows_for_k(k) above that.
 // ---------------------------------------------------------------------------
 struct TuneCache {
   std::mutex mu;
@@ -53,9 +56,11 @@ int size_class(int64_t ntiles) {
   return c;
 }
 
+int k_class(int k) { return k <= tqi::kGroupMaxK ? 0 : tqi::rows_for_k(k); }
+
 std::string tune_key(const tqi::DbDev &db, int k, int bucket) {
   char b[80];
-  std::snprintf(b, sizeof b, "nc%d/r%d/b%d/t%d", db.nc, tqi::rows_for_k(k), bucket, size_class(db.ntiles));
+  std::snprintf(b, sizeof b, "nc%d/kc%d/b%d/t%d", db.nc, k_class(k), bucket, size_class(db.ntiles));
   return b;
 }
 
@@ -335,9 +340,18 @@ int run_chunk_on(tq_db *db, BatchEntry *e, const uint32_t *qcodes, int nq, int k
 // Engine and query tile of a call: explicit options first, then the tuning
 // cache, then the default.  An explicit query tile implies its engine (2..16:
 // popcount, 64 / 128: matrix).
+// A shape the kernels accept for this k (a cache file written by another
+// build, or edited by hand, may hold one they do not).
+bool shape_valid(const Shape &sh, int k) {
+  if (sh.grid < 1) return false;
+  if (sh.engine == TQ_ENGINE_MATRIX) return tqi::rows_for_k(k) <= 2 && tqi::mfma_supported(k, sh.qtile);
+  if (sh.engine != TQ_ENGINE_POPCOUNT) return false;
+  return (sh.qtile == 2 || sh.qtile == 4 || sh.qtile == 8 || sh.qtile == 16) && sh.qtile <= tqi::batched_max_qtile(k);
+}
+
 Shape shape_for(tq_db *db, int k, int bucket, const tq_search_opts *opts) {
   Shape sh;
-  if (!tune_lookup(db->dev, k, bucket, &sh)) sh = default_shape(db, k, bucket);
+  if (!tune_lookup(db->dev, k, bucket, &sh) || !shape_valid(sh, k)) sh = default_shape(db, k, bucket);
   int engine = opts ? opts->engine : TQ_ENGINE_AUTO;
   const int qtile = opts ? opts->qtile : 0;
   if (engine == TQ_ENGINE_AUTO && qtile > 0) engine = qtile >= 64 ? TQ_ENGINE_MATRIX : TQ_ENGINE_POPCOUNT;
@@ -370,7 +384,7 @@ int choose_path(tq_db *db, int requested, int nq, int k) {
   if (requested != TQ_PATH_AUTO) return requested;
   const int bucket = bucket_of(std::min(nq, kMaxBucket));
   Shape sh;
-  if (!tune_lookup(db->dev, k, bucket, &sh)) sh = default_shape(db, k, bucket);
+  if (!tune_lookup(db->dev, k, bucket, &sh) || !shape_valid(sh, k)) sh = default_shape(db, k, bucket);
   return sh.plain ? TQ_PATH_PLAIN : TQ_PATH_BATCHED;
 }
 
@@ -417,15 +431,20 @@ void batched_release(tq_db *db) {
 // autotuner
 // ---------------------------------------------------------------------------
 
-// Times `reps` runs of one configuration (plain path when sh.plain) on `s`.
+// Times one configuration (plain path when sh.plain) on `s`: a first run
+// that builds graphs and buffers, then kTuneReps timed runs; the median.
+constexpr int kTuneReps = 3;
+
 static int time_config(tq_db *db, const uint32_t *q, int nq, int k, int32_t *ids, int32_t *scores, const Shape &sh,
                        hipStream_t s, float *ms_out) {
   hipEvent_t a = nullptr, b = nullptr;
-  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    if (a) (void)hipEventDestroy(a);
     return fail(TQ_ERR_DEVICE, "hipEventCreate");
+  }
   int rc = TQ_OK;
-  float best = 1e30f;
-  for (int rep = 0; rep < 2 && rc == TQ_OK; ++rep) {
+  float times[kTuneReps];
+  for (int rep = 0; rep <= kTuneReps && rc == TQ_OK; ++rep) {
     (void)hipEventRecord(a, s);
     if (sh.plain)
       rc = search_plain(db, q, nq, k, ids, scores, 0, TQ_ENGINE_AUTO, s);
@@ -435,22 +454,73 @@ static int time_config(tq_db *db, const uint32_t *q, int nq, int k, int32_t *ids
     if (hipEventSynchronize(b) != hipSuccess) rc = fail(TQ_ERR_DEVICE, "hipEventSynchronize");
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, a, b);
-    if (rep > 0) best = std::min(best, ms);  // the first run builds graphs and buffers
+    if (rep > 0) times[rep - 1] = ms;
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
-  *ms_out = best;
+  std::sort(times, times + kTuneReps);
+  *ms_out = rc == TQ_OK ? times[kTuneReps / 2] : 1e30f;
   return rc;
+}
+
+// splitmix64 (Steele, Lea, Flood 2014): the seeded generator of the tuning
+// queries.
+static uint64_t splitmix64(uint64_t &state) {
+  uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Tuning queries: distinct codes near the data but not in it.  Each starts
+// as a database row (canonical layout, host memory) and a quarter of its
+// non-zeros move to random zero coordinates with random signs, so the number
+// of non-zeros (the database's x) is kept; where a row has no zero
+// coordinate (x = d) those non-zeros flip sign instead.
+static void perturb_rows(uint32_t *rows, int count, int d, int W, uint64_t seed) {
+  std::vector<int> nz, zero;
+  for (int r = 0; r < count; ++r) {
+    uint64_t st = seed ^ (0xD1B54A32D192ED03ull * static_cast<uint64_t>(r + 1));
+    uint32_t *plus = rows + static_cast<size_t>(r) * 2 * W, *minus = plus + W;
+    nz.clear();
+    zero.clear();
+    for (int i = 0; i < d; ++i) {
+      const uint32_t bit = 1u << (i % 32);
+      ((plus[i / 32] | minus[i / 32]) & bit ? nz : zero).push_back(i);
+    }
+    const int moves = std::max<int>(nz.empty() ? 0 : 1, static_cast<int>(nz.size()) / 4);
+    for (int m = 0; m < moves; ++m) {
+      const size_t a = splitmix64(st) % nz.size();
+      const int i = nz[a];
+      const uint32_t bi = 1u << (i % 32);
+      const bool neg = (splitmix64(st) & 1) != 0;
+      if (zero.empty()) {  // x = d: flip the sign
+        plus[i / 32] ^= bi;
+        minus[i / 32] ^= bi;
+        continue;
+      }
+      const size_t b = splitmix64(st) % zero.size();
+      const int j = zero[b];
+      const uint32_t bj = 1u << (j % 32);
+      plus[i / 32] &= ~bi;
+      minus[i / 32] &= ~bi;
+      (neg ? minus : plus)[j / 32] |= bj;
+      nz[a] = j;  // j is now a non-zero, i a zero
+      zero[b] = i;
+    }
+  }
 }
 
 int autotune(tq_db *db, int nq_max, const int *ks, int nks, hipStream_t s, int verbose) {
   const int maxb = bucket_of(std::min(std::max(nq_max, 1), kMaxBucket));
-  // queries: copies of the first database rows (valid codes of the right (d, x))
+  // queries: the first database rows (valid codes of the right (d, x)),
+  // repeated up to the largest bucket, each perturbed in its own way
   const int nqq = std::min<int64_t>(maxb, db->dev.n);
   uint32_t *q = nullptr;
   int32_t *ids = nullptr, *scores = nullptr;
   const int W = db->dev.W;
-  hipError_t err = hipMalloc(&q, static_cast<size_t>(maxb) * 2 * W * sizeof(uint32_t));
+  const size_t row_bytes = static_cast<size_t>(2 * W) * sizeof(uint32_t);
+  hipError_t err = hipMalloc(&q, static_cast<size_t>(maxb) * row_bytes);
   int kmax = 1;
   for (int i = 0; i < nks; ++i) kmax = std::max(kmax, ks[i]);
   if (err == hipSuccess) err = hipMalloc(&ids, static_cast<size_t>(maxb) * kmax * sizeof(int32_t));
@@ -458,11 +528,16 @@ int autotune(tq_db *db, int nq_max, const int *ks, int nks, hipStream_t s, int v
   tqi::DbDev head = db->dev;
   head.n = nqq;
   head.ntiles = (nqq + 63) / 64;
+  std::vector<uint32_t> host(static_cast<size_t>(maxb) * 2 * W);
   if (err == hipSuccess) err = tqi::export_launch(head, q, s);
-  for (int r = nqq; err == hipSuccess && r < maxb; r += nqq) {
-    const int m = std::min(nqq, maxb - r);
-    err = hipMemcpyAsync(q + static_cast<size_t>(r) * 2 * W, q, static_cast<size_t>(m) * 2 * W * sizeof(uint32_t),
-                         hipMemcpyDeviceToDevice, s);
+  if (err == hipSuccess) err = hipMemcpyAsync(host.data(), q, nqq * row_bytes, hipMemcpyDeviceToHost, s);
+  if (err == hipSuccess) err = hipStreamSynchronize(s);
+  if (err == hipSuccess) {
+    for (int r = nqq; r < maxb; r += nqq)
+      std::memcpy(host.data() + static_cast<size_t>(r) * 2 * W, host.data(),
+                  static_cast<size_t>(std::min(nqq, maxb - r)) * row_bytes);
+    perturb_rows(host.data(), maxb, db->dev.d, W, 0x7E57C0DE2506ull);
+    err = hipMemcpyAsync(q, host.data(), maxb * row_bytes, hipMemcpyHostToDevice, s);
   }
   if (err == hipSuccess) err = hipStreamSynchronize(s);
   int rc = err == hipSuccess ? TQ_OK : hip_fail(err, "autotune set-up");

@@ -146,6 +146,19 @@ def test_autotune_then_auto(tq, o, small, tmp_path, monkeypatch):
             assert np.array_equal(sc, es) and np.array_equal(ids, ei), (nq, k)
 
 
+def test_autotune_large_buckets_then_other_k(tq, o, small):
+    """Tuning k = 10 up to the 512-query bucket may store 256-query matrix
+    tiles, which only k <= 16 supports; later automatic searches with k in
+    other classes (17..64, 65..128, > 128) at those bucket sizes must not take
+    that shape, and stay exact."""
+    say("autotune to the 512 bucket at k=10, then auto at other k")
+    tq.tq_autotune(small["db"], 512, [10])
+    for nq, k in ((300, 50), (300, 17), (500, 100), (260, 200), (300, 10)):
+        ids, sc = run(tq, small["db"], small["CQ"][:nq], k, path=tq.TQ_PATH_AUTO)
+        ei, es = o.knn(small["VQ"][:nq], small["V"], k)
+        assert np.array_equal(sc, es) and np.array_equal(ids, ei), (nq, k)
+
+
 # ---------------------------------------------------------------------------
 # the matrix-core engine (fp4 MFMA): same results, bit for bit
 # ---------------------------------------------------------------------------
@@ -294,7 +307,7 @@ def test_popcount_cross_part_bound_adversarial(tq, o, grid):
 
 def test_autotune_cache_file(tq, o, small, tmp_path, monkeypatch):
     """tq_autotune writes its choices to TQ_TUNE_CACHE, keyed by plane width,
-    list rows, batch-size bucket and the database's size class; searches that
+    k class, batch-size bucket and the database's size class; searches that
     use them are still exact."""
     import json
     import re
@@ -303,7 +316,7 @@ def test_autotune_cache_file(tq, o, small, tmp_path, monkeypatch):
     say("autotune cache file")
     tq.tq_autotune(small["db"], 16, [10])
     data = json.loads(path.read_text())
-    assert data and all(re.fullmatch(r"nc\d+/r\d+/b\d+/t\d+", key) for key in data), list(data)[:4]
+    assert data and all(re.fullmatch(r"nc\d+/kc\d+/b\d+/t\d+", key) for key in data), list(data)[:4]
     assert {"qtile", "grid", "plain", "engine"} <= set(next(iter(data.values())))
     for nq in (1, 9, 16):
         ids, sc = run(tq, small["db"], small["CQ"][:nq], 10, path=tq.TQ_PATH_AUTO)

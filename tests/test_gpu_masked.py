@@ -4,8 +4,10 @@ different orders, so a float score may differ by one unit in the last place
 where the double sum lies within ~1e-12 of a rounding boundary.  Where every
 score of a query matches (the normal case) the ids must match exactly; a
 query with such a boundary case is checked by properties instead (every
-returned score is the rounded scalar product of its id, the order is (score
-desc, id asc), and nothing left out beats the k-th)."""
+returned score is the rounded scalar product of its id, and a score that
+differs from it lies next to a rounding boundary; the order is (score desc, id
+asc); nothing left out beats the k-th), and at most MAX_FALLBACK queries of a
+call may need that."""
 import sys
 
 import numpy as np
@@ -38,21 +40,38 @@ def dev_codes(c):
     return torch.from_numpy(np.ascontiguousarray(c).view(np.int32).copy()).cuda()
 
 
+# Queries of one call that may be checked by properties instead of equality
+# (rounding-boundary cases are rare: a double sum lies within ~1e-12 of a
+# float rounding boundary for roughly one score in 10^4 to 10^5).
+MAX_FALLBACK = 2
+
+
 def check(gi, gs, ei, es, Q, V, exact_required=False):
     full = None
+    fallback = 0
     for q in range(ei.shape[0]):
         if np.array_equal(gs[q], es[q]):
             assert np.array_equal(gi[q], ei[q]), q
             continue
         assert not exact_required, f"query {q}: scores differ"
+        fallback += 1
+        say(f"masked: query {q} differs from the oracle; checked by properties")
+        assert fallback <= MAX_FALLBACK, f"{fallback} of {ei.shape[0]} queries differ from the oracle"
         if full is None:
             full = Q.astype(np.float64) @ V.astype(np.float64).T
         row = full[q]
         k = gi.shape[1]
         assert len(set(gi[q].tolist())) == k
         for j in range(k):
-            f = np.float32(row[gi[q, j]])
-            assert abs(float(gs[q, j]) - float(f)) <= float(np.spacing(np.float32(abs(f)))), (q, j)
+            s = float(row[gi[q, j]])
+            f = np.float32(s)
+            g = float(gs[q, j])
+            if g != float(f):
+                # one unit in the last place, and only where the double sum
+                # lies next to the boundary between the two floats
+                assert abs(g - float(f)) <= float(np.spacing(np.float32(abs(f)))), (q, j)
+                boundary = (g + float(f)) / 2
+                assert abs(s - boundary) <= 1e-12 * abs(s), (q, j, "score differs away from a rounding boundary")
             if j:
                 assert gs[q, j - 1] > gs[q, j] or (gs[q, j - 1] == gs[q, j] and gi[q, j - 1] < gi[q, j])
         rest = np.setdiff1d(np.arange(V.shape[0]), gi[q])
