@@ -223,6 +223,23 @@ enum tq_engine {
 int tq_search_knn(const tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids,
                   int32_t *scores, const tq_search_opts *opts, void *stream);
 
+/* tq_search_knn for callers that cannot allocate device memory during the
+ * call (code under HIP graph capture, tight serving loops, hosts that forbid
+ * it): the plain path only (opts->path AUTO or PLAIN; engine AUTO, POPCOUNT or
+ * SPARSE; check_queries must be 0), with the same arguments, ownership and
+ * results as tq_search_knn.  The scratch it needs (per query, grid x k 8-byte
+ * keys plus a few rows) comes from a fixed 16 MiB device array inside the
+ * library, one per GPU, held until the process ends; queries are processed in
+ * rounds that fit it.  TQ_ERR_INVALID before anything is queued if one query
+ * needs more than 16 MiB (only a grid above 4000 workgroups at k = 512, or
+ * the like, can).  The call allocates nothing and times nothing; the first
+ * call on a device looks up the array's device address.  Every such call on
+ * one GPU shares the array: calls whose GPU work may overlap (other streams,
+ * or other host threads on the same stream) race and must be serialised by
+ * the caller. */
+int tq_search_knn_noalloc(const tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids,
+                          int32_t *scores, const tq_search_opts *opts, void *stream);
+
 /* Time the candidate shapes of the batched path (query tile, workgroups) and
  * the plain path for every batch-size bucket (powers of two up to
  * min(nq_max, 1024)) and each of the nks values of k in `ks` (host array),

@@ -25,7 +25,7 @@ ARCH = os.environ.get("TQ_OFFLOAD_ARCH", "gfx950")
 # width (16-byte chunks per plane, 1..8) so their instantiations build in
 # parallel; every other source is compiled once.  Slowest first.
 SOURCES = [("mfma_kernels.hip", nc) for nc in range(8, 0, -1)] + \
-          [("scan.hip", 0), ("batched_kernels.hip", 0), ("encode.hip", 0), ("layout.hip", 0), ("rerank.hip", 0), ("masked.hip", 0), ("sparse.hip", 0),
+          [("scan.hip", 0), ("batched_kernels.hip", 0), ("encode.hip", 0), ("layout.hip", 0), ("rerank.hip", 0), ("masked.hip", 0), ("sparse.hip", 0), ("noalloc.hip", 0),
            ("api.cpp", 0), ("search.cpp", 0), ("batched.cpp", 0), ("serve.cpp", 0)]
 
 CFLAGS = [

@@ -125,8 +125,8 @@ hipEvent_t pooled_event() {
 
 bool timing_enabled() { return g_timing_on.load(std::memory_order_relaxed) != 0; }
 
-TimedLaunch::TimedLaunch(int family, hipStream_t s) : family_(family), s_(s) {
-  if (!g_timing_on.load(std::memory_order_relaxed)) return;
+TimedLaunch::TimedLaunch(int family, hipStream_t s, bool allow) : family_(family), s_(s) {
+  if (!allow || !g_timing_on.load(std::memory_order_relaxed)) return;
   std::lock_guard<std::mutex> g(g_timing.mu);
   a_ = pooled_event();
   b_ = pooled_event();

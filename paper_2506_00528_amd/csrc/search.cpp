@@ -41,7 +41,7 @@ static int default_sparse_grid(const tq_db *db) {
 }
 
 int search_plain(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids, int32_t *scores, int grid,
-                 int engine, hipStream_t s) {
+                 int engine, hipStream_t s, const ScratchSpan *ext) {
   const bool sparse = engine == TQ_ENGINE_SPARSE || (engine == TQ_ENGINE_AUTO && tqi::sparse_preferred(db->dev));
   if (sparse && !db->dev.sparse) return fail(TQ_ERR_INVALID, "no index-list copy of this database");
   const int G = grid > 0 ? grid : sparse ? default_sparse_grid(db) : default_plain_grid(db);
@@ -53,11 +53,26 @@ int search_plain(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids,
   const bool sampled = !sparse && db->dev.ntiles >= kSampleMinTiles && use_sample(per_wave, k);
   const size_t per_query = static_cast<size_t>(G) * k * sizeof(uint64_t);
   const size_t per_query_all = per_query + (sampled ? 2 * static_cast<size_t>(k) * sizeof(int32_t) : 0);
-  const int chunk = static_cast<int>(std::max<size_t>(1, std::min<size_t>(nq, kPartialBudget / per_query_all)));
-  const size_t mid_keys = static_cast<size_t>(tqi::merge_mid_keys(chunk, G, k));
+  int chunk;
   void *p = nullptr;
-  int rc = scratch_get(db->scratch, s, per_query_all * chunk + mid_keys * sizeof(uint64_t), &p);
-  if (rc) return rc;
+  if (ext) {
+    // A caller's fixed buffer: as many queries per merge round as fit, with
+    // the merge's intermediate keys (linear in the round's query count).
+    const size_t need1 = per_query_all + static_cast<size_t>(tqi::merge_mid_keys(1, G, k)) * sizeof(uint64_t);
+    if (need1 > ext->bytes)
+      return fail(TQ_ERR_INVALID, "grid=%d, k=%d needs %zu bytes of scratch per query, more than the %zu available",
+                  G, k, need1, ext->bytes);
+    chunk = static_cast<int>(std::min<size_t>(nq, ext->bytes / need1));
+    p = ext->p;
+  } else {
+    chunk = static_cast<int>(std::max<size_t>(1, std::min<size_t>(nq, kPartialBudget / per_query_all)));
+  }
+  const size_t mid_keys = static_cast<size_t>(tqi::merge_mid_keys(chunk, G, k));
+  if (!ext) {
+    int rc = scratch_get(db->scratch, s, per_query_all * chunk + mid_keys * sizeof(uint64_t), &p);
+    if (rc) return rc;
+  }
+  const bool timed = ext == nullptr;  // event creation stays off the no-allocation path
   uint64_t *partial = static_cast<uint64_t *>(p);
   uint64_t *mid = partial + static_cast<size_t>(chunk) * G * k;
   // sample results: chunk x k ids, then chunk x k scores
@@ -70,7 +85,7 @@ int search_plain(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids,
       tqi::PlainScanOpts o;
       o.tstride = kSampleStride;
       for (int i = 0; i < nc; ++i) {
-        TimedLaunch t(kTimePlain, s);
+        TimedLaunch t(kTimePlain, s, timed);
         hipError_t e = tqi::scan_plain_launch(db->dev, qcodes + static_cast<int64_t>(q0 + i) * row_words, k, G,
                                               partial + static_cast<size_t>(i) * G * k, s, o);
         if (e != hipSuccess) return hip_fail(e, "sample scan launch");
@@ -79,7 +94,7 @@ int search_plain(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids,
       if (e != hipSuccess) return hip_fail(e, "sample merge launch");
     }
     for (int i = 0; i < nc; ++i) {
-      TimedLaunch t(sparse ? kTimeSparse : kTimePlain, s);
+      TimedLaunch t(sparse ? kTimeSparse : kTimePlain, s, timed);
       const uint32_t *qc = qcodes + static_cast<int64_t>(q0 + i) * row_words;
       uint64_t *dst = partial + static_cast<size_t>(i) * G * k;
       tqi::PlainScanOpts o;

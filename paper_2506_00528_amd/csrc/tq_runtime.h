@@ -49,7 +49,8 @@ bool timing_enabled();
 // Brackets one kernel launch with HIP events on stream `s` when timing is on.
 class TimedLaunch {
  public:
-  TimedLaunch(int family, hipStream_t s);
+  // `allow` = false leaves the launch untimed whatever tq_timing_enable says.
+  TimedLaunch(int family, hipStream_t s, bool allow = true);
   ~TimedLaunch();
   TimedLaunch(const TimedLaunch &) = delete;
   TimedLaunch &operator=(const TimedLaunch &) = delete;
@@ -66,6 +67,11 @@ struct Scratch {
   size_t bytes = 0;
 };
 using ScratchMap = std::unordered_map<hipStream_t, Scratch>;
+// A caller-provided device buffer used in place of scratch_get().
+struct ScratchSpan {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
 // Buffer of at least `bytes` private to (owner, stream); growing it waits for
 // the stream first.  The owner's mutex must be held.
 int scratch_get(ScratchMap &map, hipStream_t s, size_t bytes, void **out);
@@ -94,8 +100,10 @@ namespace tqr {
 int default_plain_grid(const tq_db *db);
 // engine: TQ_ENGINE_SPARSE takes the index-list scan, TQ_ENGINE_AUTO takes it
 // where sparse_preferred(), anything else the bit-plane scan.
+// With `ext` the scratch comes from that buffer (nothing is allocated and no
+// launch is timed); TQ_ERR_INVALID if one query's need does not fit in it.
 int search_plain(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids, int32_t *scores, int grid,
-                 int engine, hipStream_t s);
+                 int engine, hipStream_t s, const ScratchSpan *ext = nullptr);
 int search_masked(tq_db *db, const float *Q, int nq, int k, int32_t *ids, float *scores, int grid, hipStream_t s);
 
 // batched.cpp

@@ -45,7 +45,7 @@ EXPORTS = (
     "tq_db_export", "tq_db_info", "tq_db_destroy", "tq_search_knn", "tq_autotune", "tq_delta_dump", "tq_sync",
     "tq_serve_create", "tq_serve_submit", "tq_serve_poll", "tq_serve_wait", "tq_serve_cancel",
     "tq_serve_stats", "tq_serve_destroy", "tq_timing_enable", "tq_timing_read", "tq_rerank",
-    "tq_search_masked", "tq_default_x", "tq_encode_b158",
+    "tq_search_masked", "tq_default_x", "tq_encode_b158", "tq_search_knn_noalloc",
 )
 
 
@@ -100,6 +100,7 @@ def lib(path: Optional[str] = None):
         "tq_db_info": ([vp, P(i64), P(i32), P(i32), P(sz)], i32),
         "tq_db_destroy": ([vp], i32),
         "tq_search_knn": ([vp, vp, i32, i32, vp, vp, P(tq_search_opts), vp], i32),
+        "tq_search_knn_noalloc": ([vp, vp, i32, i32, vp, vp, P(tq_search_opts), vp], i32),
         "tq_autotune": ([vp, i32, P(i32), i32, vp], i32),
         "tq_delta_dump": ([vp, vp, i32, vp, vp], i32),
         "tq_rerank": ([vp, i64, i32, vp, i32, vp, i32, i32, vp, vp, vp], i32),
@@ -295,6 +296,23 @@ def tq_search_knn(db: tq_db, qcodes: torch.Tensor, k: int, path: int = TQ_PATH_A
                                    _dev(ids, "ids", torch.int32), _dev(scores, "scores", torch.int32),
                                    ctypes.byref(o), _stream(qcodes, stream)), "tq_search_knn")
     return ids, scores
+
+
+def tq_search_knn_noalloc(db: tq_db, qcodes: torch.Tensor, k: int, ids: torch.Tensor, scores: torch.Tensor,
+                          path: int = TQ_PATH_PLAIN, grid: int = 0, engine: int = TQ_ENGINE_AUTO,
+                          check_queries: bool = False, stream=None) -> None:
+    """tq_search_knn's plain path into caller-provided ids / scores, with the
+    library's fixed scratch array (no device allocation in the call)."""
+    if qcodes.dim() != 2 or qcodes.shape[1] != 2 * db.W:
+        raise ValueError("qcodes must be nq x 2W for the database's d")
+    nq = int(qcodes.shape[0])
+    if tuple(ids.shape) != (nq, k) or tuple(scores.shape) != (nq, k):
+        raise ValueError("ids and scores must be nq x k")
+    with torch.cuda.device(db.device):
+        o = _opts(path, check_queries, grid, 0, 1, engine)
+        _check(lib().tq_search_knn_noalloc(db.handle, _dev(qcodes, "qcodes", torch.int32), nq, int(k),
+                                           _dev(ids, "ids", torch.int32), _dev(scores, "scores", torch.int32),
+                                           ctypes.byref(o), _stream(qcodes, stream)), "tq_search_knn_noalloc")
 
 
 def tq_autotune(db: tq_db, nq_max: int, ks, stream=None) -> None:
