@@ -5,16 +5,14 @@ mid (N = 1e6, d = 768, x in {96, 192, 384}): every code against the oracle's,
 and top-100 of sampled queries (plain and batched) against the oracle's
 exhaustive search over the oracle's own codes.
 
-large (N = 1e7, d = 1024, x = 256): the oracle cannot encode all 10^7 rows in a
-test's time, so codes are compared on sampled chunks, and each sampled
-query's top-10 is checked by properties that hold at any size: every returned
-score equals the oracle's Delta for that (query, row); results are ordered
-(Delta desc, id asc); and no row of the sampled chunks that is not in the
-result beats the k-th result.  Plain and batched results must be identical,
-also for batches of 40 to 600 queries at k = 1, 10 and 100, and the
-index-list engine on the same rows at x = d / 32 equals the bit-plane scan;
-masked addition of the float queries is checked by the same kind of
-properties.
+large (N = 1e7, d = 1024, x = 256): every code against the oracle's, chunk by
+chunk; the exact top-100 of 18 sampled queries, from a running merge of the
+oracle's search of each chunk (a top-k under the total order is the merge of
+the top-k of disjoint parts, which the oracle pins check), against the plain
+path (k = 10, 100) and the batched path at batch sizes 12 to 600 and
+k = 1, 10, 100, with default and autotuned shapes; masked addition of float
+queries against the oracle's masked top-10 built the same way; and the
+index-list engine on the same rows at x = d / 32 equals the bit-plane scan.
 
 serving (N = 5e6, d = 768, x = 192): a mix of requests served concurrently
 gives the plain path's rows.
@@ -82,116 +80,146 @@ def test_mid_full_parity(tq, o, mid_data, x):
     db.destroy()
 
 
-def test_large_sampled(tq, o):
+def merge_running(run, add, K):
+    """Merge two per-query key lists (ids, scores) into the K best by
+    (score desc, id asc): the oracle's order, applied to partial results of
+    disjoint row ranges (order independence is pinned on the oracle)."""
+    if run is None:
+        return add[0][:, :K].copy(), add[1][:, :K].copy()
+    ids = np.concatenate([run[0], add[0]], 1)
+    sc = np.concatenate([run[1], add[1]], 1)
+    out_i = np.empty((ids.shape[0], K), dtype=ids.dtype)
+    out_s = np.empty((ids.shape[0], K), dtype=sc.dtype)
+    for q in range(ids.shape[0]):
+        order = np.lexsort((ids[q], -sc[q].astype(np.float64)))[:K]
+        out_i[q], out_s[q] = ids[q, order], sc[q, order]
+    return out_i, out_s
+
+
+# Queries of the 600-query pool whose exact top-100 the oracle computes over
+# all 10^7 rows: the first and last rows of query tiles of 16, 64, 128 and 256
+# queries and of the batch sizes below.
+SAMPLED = [0, 1, 5, 11, 15, 16, 63, 64, 127, 128, 129, 255, 256, 299, 383, 511, 512, 599]
+MASKED_Q = 4       # float queries whose exact masked-addition top-10 the oracle computes
+MASKED_KEEP = 32   # oracle candidates kept per masked query (more than k, for the property check)
+
+
+def test_large_exact(tq, o):
+    """Every code of the 10^7 rows equals the oracle's; the exact oracle top-100
+    of 18 sampled queries (a running merge over the oracle's search of each
+    chunk) equals the plain path's top-10 / top-100 and the batched path's
+    rows at batch sizes 12 ... 600 and k = 1, 10, 100, with default and with
+    autotuned shapes; masked addition of 4 float queries equals the oracle's
+    masked top-10."""
     w = datagen.WORKLOADS["large"]
     n, d, x, k = w["n"], w["d"], w["x"], w["k"]
     dev = torch.device("cuda", 0)
     W = tq.tq_code_words(d)
     nchunks = (n + datagen.CHUNK - 1) // datagen.CHUNK
-    sample_chunks = [0, 47, 101, nchunks - 1]
-    say(f"large full size: generate + encode N={n} d={d} x={x}")
+    Q2 = datagen.rows(w["spec"], datagen.QUERIES, 0, 600, dev)
+    qc2 = tq.tq_encode(Q2, x)
+    VQS = o.encode(Q2[SAMPLED].cpu().numpy(), x)
+    QM = Q2[:MASKED_Q].cpu().numpy()
     codes = torch.empty((n, 2 * W), dtype=torch.int32, device=dev)
     xs = d // 32  # the same rows at a small x, for the index-list engine
     codes_s = torch.empty((n, 2 * W), dtype=torch.int32, device=dev)
-    sampled = {}
-    for r0, Xc in datagen.iter_rows(w["spec"], datagen.DB, 0, n, dev):
-        tq.tq_encode(Xc, x, codes[r0:r0 + Xc.shape[0]])
-        tq.tq_encode(Xc, xs, codes_s[r0:r0 + Xc.shape[0]])
-        if r0 // datagen.CHUNK in sample_chunks:
-            sampled[r0] = Xc.cpu().numpy()
-    Q = datagen.rows(w["spec"], datagen.QUERIES, 0, 4, dev)
-    qcodes = tq.tq_encode(Q, x)
-    tq.tq_sync()
-    say("large full size: sampled codes against the oracle")
-    oracle_rows = {}
-    for r0, Xh in sampled.items():
+    top = None   # oracle top-100 of the sampled queries so far
+    mtop = None  # oracle masked-addition candidates so far (ids, float scores)
+    mexact = {}  # id -> exact double sum, per masked query, for kept candidates
+    say(f"large full size: generate + encode N={n} d={d} x={x}; oracle encode and search of every chunk")
+    for c, (r0, Xc) in enumerate(datagen.iter_rows(w["spec"], datagen.DB, 0, n, dev)):
+        m = Xc.shape[0]
+        tq.tq_encode(Xc, x, codes[r0:r0 + m])
+        tq.tq_encode(Xc, xs, codes_s[r0:r0 + m])
+        Xh = Xc.cpu().numpy()
         V = o.encode(Xh, x)
-        oracle_rows[r0] = V
-        assert np.array_equal(codes[r0:r0 + Xh.shape[0]].cpu().numpy().view(np.uint32), o.pack(V)), r0
+        assert np.array_equal(codes[r0:r0 + m].cpu().numpy().view(np.uint32), o.pack(V)), f"codes of chunk {c}"
+        ci, cs = o.knn(VQS, V, min(100, m))
+        top = merge_running(top, (ci.astype(np.int64) + r0, cs), 100)
+        mi, ms, me = o.masked_knn(QM, V, min(MASKED_KEEP, m))
+        for q in range(MASKED_Q):
+            for j in range(mi.shape[1]):
+                mexact[(q, int(mi[q, j]) + r0)] = float(me[q, j])
+        mtop = merge_running(mtop, (mi.astype(np.int64) + r0, ms), MASKED_KEEP)
+        if c % 16 == 0 or c == nchunks - 1:
+            say(f"large full size: chunk {c + 1}/{nchunks} codes equal the oracle's")
+    tq.tq_sync()
     db = tq.tq_db_create(codes, d, x)
     del codes
-    say("large full size: top-10 plain and batched")
-    ip, sp = tq.tq_search_knn(db, qcodes, k, path=tq.TQ_PATH_PLAIN)
-    ib, sb = tq.tq_search_knn(db, qcodes, k, path=tq.TQ_PATH_BATCHED)
-    torch.cuda.synchronize()
-    assert torch.equal(ip, ib) and torch.equal(sp, sb), "plain and batched differ"
-    ids, scores = ip.cpu().numpy(), sp.cpu().numpy()
-    VQ = o.encode(Q.cpu().numpy(), x)
-    # every returned score is the oracle's Delta for that row
-    need = sorted(set(ids.ravel().tolist()))
-    rows = torch.empty((len(need), d), dtype=torch.float32)
-    for j, r in enumerate(need):
-        c = r // datagen.CHUNK
-        blk = datagen.chunk(datagen.SPECS[w["spec"]], datagen.DB, c, dev)
-        rows[j] = blk[r - c * datagen.CHUNK].cpu()
-    VR = o.encode(rows.numpy(), x)
-    D = o.delta(VQ, VR)
-    pos = {r: j for j, r in enumerate(need)}
-    for q in range(4):
-        for j in range(k):
-            assert scores[q, j] == D[q, pos[ids[q, j]]], (q, j)
-        keys = [key_of(scores[q, j], ids[q, j]) for j in range(k)]
-        assert keys == sorted(keys, reverse=True), "not ordered"
-        kth = keys[-1]
-        chosen = set(ids[q].tolist())
-        for r0, V in oracle_rows.items():
-            Ds = o.delta(VQ[q:q + 1], V)[0]
-            for i in np.nonzero(Ds >= kth[0])[0]:
-                rid = r0 + int(i)
-                if rid not in chosen:
-                    assert key_of(Ds[i], rid) < kth, f"row {rid} beats the k-th result of query {q}"
-    # the batched path at the batching workload's batch sizes and k (matrix
-    # engine: 256-query tiles for k <= 16, 128- and 64-query tiles for k = 100)
-    # gives the same bits as the plain path
-    Q2 = datagen.rows(w["spec"], datagen.QUERIES, 100, 600, dev)
-    qc2 = tq.tq_encode(Q2, x)
-    for nq, kk in ((600, 1), (600, 10), (300, 100), (40, 100)):
-        say(f"large full size: batched vs plain nq={nq} k={kk}")
-        ib2, sb2 = tq.tq_search_knn(db, qc2[:nq], kk, path=tq.TQ_PATH_BATCHED)
-        ip2, sp2 = tq.tq_search_knn(db, qc2[:nq], kk, path=tq.TQ_PATH_PLAIN)
+    ei, es = top
+
+    def check_rows(ids, scores, rows, kk, what):
+        ids, scores = ids.cpu().numpy(), scores.cpu().numpy()
+        for r in rows:
+            j = SAMPLED.index(r)
+            assert np.array_equal(scores[r], es[j, :kk]), f"{what}: scores of query {r}"
+            assert np.array_equal(ids[r], ei[j, :kk]), f"{what}: ids of query {r}"
+
+    say("large full size: plain path top-10 and top-100 of the sampled queries")
+    qs = qc2[SAMPLED]
+    for kk in (10, 100):
+        ip, sp = tq.tq_search_knn(db, qs, kk, path=tq.TQ_PATH_PLAIN)
         torch.cuda.synchronize()
-        assert torch.equal(ib2, ip2) and torch.equal(sb2, sp2), (nq, kk)
-    # masked addition of the float queries, checked by properties: every
-    # returned score is the float rounding of the scalar product with the row's
-    # ternary code (one unit in the last place: both sides sum in double, in
-    # different orders), the order is (score desc, id asc), and no row of the
-    # sampled chunks left out beats the k-th by more than that unit
-    say("large full size: masked addition top-10")
-    mi, ms = tq.tq_search_masked(db, Q, k)
+        ip, sp = ip.cpu().numpy(), sp.cpu().numpy()
+        assert np.array_equal(sp, es[:, :kk]) and np.array_equal(ip, ei[:, :kk]), f"plain k={kk}"
+    # the batched path at the batching workload's sizes and k (both engines'
+    # tiles: 16-query popcount tiles, 64 / 128 / 256-query matrix tiles), with
+    # the default shapes and after the autotuner has picked its own
+    cases = ((12, 1), (12, 10), (16, 100), (130, 10), (130, 100), (300, 1), (300, 100), (600, 10), (600, 100))
+    for tuned in (False, True):
+        if tuned:
+            say("large full size: autotune (nq up to 1024, k = 1, 10, 100)")
+            tq.tq_autotune(db, 1024, [1, 10, 100])
+        for nq, kk in cases:
+            say(f"large full size: {'auto (tuned)' if tuned else 'batched'} nq={nq} k={kk} against the oracle")
+            path = tq.TQ_PATH_AUTO if tuned else tq.TQ_PATH_BATCHED
+            ib, sb = tq.tq_search_knn(db, qc2[:nq], kk, path=path)
+            torch.cuda.synchronize()
+            check_rows(ib, sb, [r for r in SAMPLED if r < nq], kk, f"nq={nq} k={kk} tuned={tuned}")
+            if not tuned and nq in (12, 300, 600):
+                ip2, sp2 = tq.tq_search_knn(db, qc2[:nq], kk, path=tq.TQ_PATH_PLAIN)
+                torch.cuda.synchronize()
+                assert torch.equal(ib, ip2) and torch.equal(sb, sp2), ("batched vs plain", nq, kk)
+    # masked addition of the float queries against the oracle's masked
+    # top-10 (both sum in double and round once; a query whose float scores
+    # differ -- a double sum within ~1e-12 of a rounding boundary -- is
+    # checked by properties, at most one of the four)
+    say("large full size: masked addition top-10 against the oracle")
+    gi, gs = tq.tq_search_masked(db, Q2[:MASKED_Q], k)
     torch.cuda.synchronize()
-    mi, ms = mi.cpu().numpy(), ms.cpu().numpy()
-    Qh = Q.cpu().numpy().astype(np.float64)
-    mneed = sorted(set(mi.ravel().tolist()))
-    mrows = torch.empty((len(mneed), d), dtype=torch.float32)
-    for j, r in enumerate(mneed):
-        c = r // datagen.CHUNK
-        blk = datagen.chunk(datagen.SPECS[w["spec"]], datagen.DB, c, dev)
-        mrows[j] = blk[r - c * datagen.CHUNK].cpu()
-    MV = o.encode(mrows.numpy(), x).astype(np.float64)
-    mpos = {r: j for j, r in enumerate(mneed)}
-    ulp = lambda f: float(np.spacing(np.float32(abs(f))))
-    for q in range(4):
+    gi, gs = gi.cpu().numpy(), gs.cpu().numpy()
+    oi, osc = mtop
+    fallback = 0
+    for q in range(MASKED_Q):
+        if np.array_equal(gs[q], osc[q, :k]):
+            assert np.array_equal(gi[q], oi[q, :k]), q
+            continue
+        fallback += 1
+        assert fallback <= 1, "more than one masked query differs from the oracle"
         for j in range(k):
-            f = float(np.float32(Qh[q] @ MV[mpos[mi[q, j]]]))
-            assert abs(float(ms[q, j]) - f) <= ulp(f), (q, j)
+            assert (q, int(gi[q, j])) in mexact, (q, j, "not among the oracle's candidates")
+            s = mexact[(q, int(gi[q, j]))]
+            f, g = float(np.float32(s)), float(gs[q, j])
+            if g != f:
+                assert abs(g - f) <= float(np.spacing(np.float32(abs(f)))), (q, j)
+                assert abs(s - (g + f) / 2) <= 1e-12 * abs(s), (q, j, "differs away from a rounding boundary")
             if j:
-                assert ms[q, j - 1] > ms[q, j] or (ms[q, j - 1] == ms[q, j] and mi[q, j - 1] < mi[q, j]), (q, j)
-        lim = float(ms[q, -1]) + ulp(ms[q, -1])
-        chosen = set(mi[q].tolist())
-        for r0, V in oracle_rows.items():
-            sc = (Qh[q] @ V.astype(np.float64).T).astype(np.float32)
-            for i in np.nonzero(sc > lim)[0]:
-                assert r0 + int(i) in chosen, f"row {r0 + int(i)} beats the masked k-th of query {q}"
+                assert gs[q, j - 1] > gs[q, j] or (gs[q, j - 1] == gs[q, j] and gi[q, j - 1] < gi[q, j])
+        lim = float(gs[q, -1]) + float(np.spacing(np.float32(abs(gs[q, -1]))))
+        chosen = set(gi[q].tolist())
+        for j in range(MASKED_KEEP):
+            if int(oi[q, j]) not in chosen:
+                assert float(osc[q, j]) <= lim, (q, j, "an oracle candidate left out beats the k-th")
     db.destroy()
     # the index-list engine on the x = d / 32 codes of the same rows gives the
     # bit-plane scan's results
     db_s = tq.tq_db_create(codes_s, d, xs)
     del codes_s
-    qs = tq.tq_encode(Q2[:16], xs)
+    qs_s = tq.tq_encode(Q2[:16], xs)
     for kk in (10, 100):
         say(f"large full size: index lists vs bit planes x={xs} k={kk}")
-        i_s, s_s = tq.tq_search_knn(db_s, qs, kk, path=tq.TQ_PATH_PLAIN, engine=tq.TQ_ENGINE_SPARSE)
-        i_b, s_b = tq.tq_search_knn(db_s, qs, kk, path=tq.TQ_PATH_PLAIN, engine=tq.TQ_ENGINE_POPCOUNT)
+        i_s, s_s = tq.tq_search_knn(db_s, qs_s, kk, path=tq.TQ_PATH_PLAIN, engine=tq.TQ_ENGINE_SPARSE)
+        i_b, s_b = tq.tq_search_knn(db_s, qs_s, kk, path=tq.TQ_PATH_PLAIN, engine=tq.TQ_ENGINE_POPCOUNT)
         torch.cuda.synchronize()
         assert torch.equal(i_s, i_b) and torch.equal(s_s, s_b), kk
     db_s.destroy()

@@ -313,3 +313,34 @@ def test_search_sample_floor_large_k(tq, o, grid):
         ei, es = o.knn(VQ, V, k)
         assert np.array_equal(sc, es) and np.array_equal(ids, ei), k
     db.destroy()
+
+
+def test_search_several_tiles_per_wave(tq, o):
+    """d = 1024 codes of the large workload's mixture, n = 2^19 + 77 (8 194
+    tiles, a ragged last one) at the default grid of 512 workgroups: every
+    wave of the plain scan takes four or five tiles through its two
+    alternating load buffers, the benchmarked kernel's loop; k = 10 scans
+    directly and k = 100 after a sample pass.  The batched path (both engines)
+    on the same database too."""
+    n, d, x = (1 << 19) + 77, 1024, 256
+    dev = torch.device("cuda", 0)
+    say(f"several tiles per wave: generate + encode n={n} d={d} x={x}")
+    X = datagen.rows("large", datagen.DB, 0, n, dev)
+    Q = datagen.rows("large", datagen.QUERIES, 0, 8, dev)
+    codes = tq.tq_encode(X, x)
+    qcodes = tq.tq_encode(Q, x)
+    tq.tq_sync()
+    V, VQ = o.encode(X.cpu().numpy(), x), o.encode(Q.cpu().numpy(), x)
+    del X
+    assert np.array_equal(u32(codes), o.pack(V)), "codes differ"
+    db = tq.tq_db_create(codes, d, x)
+    del codes
+    for k in (10, 100):
+        ei, es = o.knn(VQ, V, k)
+        for path, engine in ((tq.TQ_PATH_PLAIN, tq.TQ_ENGINE_AUTO), (tq.TQ_PATH_BATCHED, tq.TQ_ENGINE_POPCOUNT),
+                             (tq.TQ_PATH_BATCHED, tq.TQ_ENGINE_MATRIX)):
+            say(f"several tiles per wave k={k} path={path} engine={engine}")
+            ids, sc = tq.tq_search_knn(db, qcodes, k, path=path, engine=engine)
+            torch.cuda.synchronize()
+            assert np.array_equal(sc.cpu().numpy(), es) and np.array_equal(ids.cpu().numpy(), ei), (k, path, engine)
+    db.destroy()
