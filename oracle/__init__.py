@@ -8,7 +8,9 @@ The arithmetic lives in ``oracle.c`` (plain C + OpenMP, built with gcc); this
 module only marshals numpy arrays (encode, pack, unpack, delta, knn, the
 refinement of proxy candidates with the float vectors, rerank, and the
 masked-addition search of float queries against ternary vectors,
-masked_knn, and the b1.58 quantisation of Sec. 4.3, encode_b158), plus a few
+masked_knn, the b1.58 quantisation of Sec. 4.3, encode_b158, and the search
+by euclidean distance between ternary vectors that codes of varying non-zero
+counts need, knn_l2), plus a few
 pure-Python definitions:
 
 * ``default_x(d)``     -- the x maximising the vertex count C(d,x)*2^x
@@ -56,6 +58,7 @@ def load(path: str | None = None):
     lib.oracle_unpack.argtypes = [vp, i64, i32, vp]
     lib.oracle_delta.argtypes = [vp, i64, vp, i64, i32, vp]
     lib.oracle_knn.argtypes = [vp, i64, vp, i64, i32, i32, vp, vp]
+    lib.oracle_knn_l2.argtypes = [vp, i64, vp, i64, i32, i32, vp, vp]
     lib.oracle_rerank.argtypes = [vp, i64, i32, vp, i64, vp, i32, i32, vp, vp]
     lib.oracle_masked_knn.argtypes = [vp, i64, vp, i64, i32, i32, vp, vp, vp]
     lib.oracle_encode_b158.argtypes = [vp, i64, i32, vp]
@@ -167,6 +170,25 @@ class Oracle:
             raise OracleError(rc, "knn")
         return ids, scores
 
+    # -- exhaustive kNN by euclidean distance of ternary vectors -----------
+    def knn_l2(self, Q: np.ndarray, V: np.ndarray, k: int):
+        """Nearest by squared l2 distance between the ternary vectors (for
+        codes of varying non-zero counts, e.g. b1.58), ties to the lower id;
+        scores are nnz(q) - distance (= 2 Delta - nnz(v))."""
+        Q = np.ascontiguousarray(Q, dtype=np.int8)
+        V = np.ascontiguousarray(V, dtype=np.int8)
+        if Q.ndim == 1:
+            Q = Q[None, :]
+        if Q.shape[1] != V.shape[1]:
+            raise ValueError("dimension mismatch")
+        nq = Q.shape[0]
+        ids = np.empty((nq, k), dtype=np.int32)
+        scores = np.empty((nq, k), dtype=np.int32)
+        rc = self.lib.oracle_knn_l2(Q.ctypes.data, nq, V.ctypes.data, V.shape[0], Q.shape[1],
+                                    int(k), ids.ctypes.data, scores.ctypes.data)
+        if rc != 0:
+            raise OracleError(rc, "knn_l2")
+        return ids, scores
 
     # -- refinement of proxy candidates (Sec. 5.3 k@n) ---------------------
     def rerank(self, X: np.ndarray, Q: np.ndarray, cand: np.ndarray, k: int):
@@ -261,6 +283,10 @@ def delta(Q, V):
 
 def knn(Q, V, k):
     return default().knn(Q, V, k)
+
+
+def knn_l2(Q, V, k):
+    return default().knn_l2(Q, V, k)
 
 
 def rerank(X, Q, cand, k):

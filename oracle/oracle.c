@@ -29,6 +29,9 @@
  *            masked addition (Sec. 5.1.2; the asymmetric variant of Sec. 6).
  *   b1.58  : the absmean ternary quantisation the paper compares against
  *            (Sec. 4.3), per embedding.
+ *   knn_l2 : exhaustive kNN by the euclidean distance between ternary vectors,
+ *            the distance a search over codes of varying non-zero counts
+ *            (b1.58) needs (Sec. 1.1, Sec. 4.3).
  *
  * Readings taken where the paper is silent (each is listed in the design notes):
  *   - equal magnitudes at the x-th place: the lower coordinate index wins;
@@ -286,6 +289,67 @@ int oracle_knn(const int8_t *Q, int64_t nq, const int8_t *V, int64_t n, int d, i
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
       all[i].score = ternary_dot(qv, V + i * (int64_t)d, d);
+      all[i].id = (int32_t)i;
+    }
+    merge_sort_scored(all, tmp, 0, n);
+    for (int j = 0; j < k; ++j) {
+      ids[q * k + j] = all[j].id;
+      scores[q * k + j] = all[j].score;
+    }
+  }
+  free(all);
+  free(tmp);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exhaustive kNN by euclidean distance between ternary vectors              */
+/* ------------------------------------------------------------------------ */
+/*
+ * Codes with a varying number of non-zeros (the b1.58 quantisation of
+ * Sec. 4.3) have varying norms, and the scalar product orders vectors by
+ * distance only when the norms are equal (Sec. 1.1 relates l2 and the scalar
+ * product for normalised vectors).  This search orders the database by the
+ * squared euclidean distance between the ternary vectors, taken coordinate by
+ * coordinate: nearest first, the lower id on equal distances.  The score it
+ * reports is nnz(q) - distance, so that larger means nearer, as for Delta
+ * (it equals 2 Delta - nnz(v)).
+ */
+static int32_t ternary_sqdist(const int8_t *a, const int8_t *b, int d) {
+  int32_t s = 0;
+  for (int i = 0; i < d; ++i) {
+    const int32_t t = (int32_t)a[i] - (int32_t)b[i];
+#if ORACLE_MUTANT == 10
+    s += t != 0; /* planted: counts differing coordinates (a Hamming distance) */
+#else
+    s += t * t;
+#endif
+  }
+  return s;
+}
+
+static int32_t ternary_nnz(const int8_t *a, int d) {
+  int32_t s = 0;
+  for (int i = 0; i < d; ++i) s += a[i] != 0;
+  return s;
+}
+
+int oracle_knn_l2(const int8_t *Q, int64_t nq, const int8_t *V, int64_t n, int d, int k,
+                  int32_t *ids, int32_t *scores) {
+  if (nq < 0 || n < 1 || n > INT32_MAX || d < 1 || k < 1 || k > n) return ORACLE_EINVAL;
+  scored_t *all = (scored_t *)malloc(sizeof(scored_t) * (size_t)n);
+  scored_t *tmp = (scored_t *)malloc(sizeof(scored_t) * (size_t)n);
+  if (!all || !tmp) {
+    free(all);
+    free(tmp);
+    return ORACLE_ENOMEM;
+  }
+  for (int64_t q = 0; q < nq; ++q) {
+    const int8_t *qv = Q + q * (int64_t)d;
+    const int32_t nnzq = ternary_nnz(qv, d);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      all[i].score = nnzq - ternary_sqdist(qv, V + i * (int64_t)d, d);
       all[i].id = (int32_t)i;
     }
     merge_sort_scored(all, tmp, 0, n);

@@ -435,10 +435,60 @@ def check_b158_properties(o, seed=16):
     assert np.array_equal(V != 0, np.abs(X.astype(np.float64)) / gamma > 0.5)
 
 
+# ---------------------------------------------------------------------------
+# kNN by euclidean distance between ternary vectors (codes of varying
+# non-zero counts, e.g. b1.58 of Sec. 4.3)
+# ---------------------------------------------------------------------------
+
+def check_knn_l2_worked(o):
+    """Hand-worked distances: q = (1, 0, -1, 0) against five codes of 0 to 4
+    non-zeros.  Squared distances 1, 2, 2, 0, 8 give the order 3, 0, 1, 2, 4
+    (equal distances: lower id first) and scores nnz(q) - distance = 2, 1, 0,
+    0, -6; the plain scalar product would rank codes 1 and 3 (Delta 2) first."""
+    Q = np.array([[1, 0, -1, 0]], dtype=np.int8)
+    V = np.array([[1, 0, 0, 0], [1, 1, -1, 1], [0, 0, 0, 0], [1, 0, -1, 0], [-1, 0, 1, 0]], dtype=np.int8)
+    ids, sc = o.knn_l2(Q, V, 5)
+    assert ids.tolist() == [[3, 0, 1, 2, 4]] and sc.tolist() == [[2, 1, 0, 0, -6]]
+
+
+def check_knn_l2_library_distance(o, seed=17):
+    """b1.58 codes (varying non-zero counts, with duplicates for ties): the
+    order is that of scipy's squared euclidean distance (lexsort, lower id on
+    ties), and every score is 2 Delta - nnz(v) by the oracle's Delta."""
+    from scipy.spatial.distance import cdist
+
+    rng = np.random.default_rng(seed)
+    for n, d, k in ((300, 24, 40), (120, 7, 120)):
+        base = o.encode_b158(rng.standard_normal((n // 3, d)).astype(np.float32))
+        V = base[rng.integers(0, base.shape[0], size=n)]
+        Q = np.concatenate([base[:2], o.encode_b158(rng.standard_normal((3, d)).astype(np.float32))])
+        ids, sc = o.knn_l2(Q, V, k)
+        dist = cdist(Q.astype(np.float64), V.astype(np.float64), "sqeuclidean")
+        D = o.delta(Q, V)
+        nnz_v = (V != 0).sum(1)
+        for q in range(Q.shape[0]):
+            order = np.lexsort((np.arange(n), dist[q]))[:k]
+            assert np.array_equal(ids[q], order), q
+            assert np.array_equal(sc[q], 2 * D[q, ids[q]] - nnz_v[ids[q]]), q
+
+
+def check_knn_l2_equal_counts_is_delta(o, seed=18):
+    """With exactly x non-zeros in every code the distance is 2x - 2 Delta, so
+    the order is the Delta order and the score 2 Delta - x."""
+    rng = np.random.default_rng(seed)
+    n, d, x, k = 400, 40, 13, 60
+    V = o.encode(rng.standard_normal((n, d)).astype(np.float32), x)
+    Q = o.encode(rng.standard_normal((5, d)).astype(np.float32), x)
+    ids, sc = o.knn_l2(Q, V, k)
+    ei, es = o.knn(Q, V, k)
+    assert np.array_equal(ids, ei) and np.array_equal(sc, 2 * es - x)
+
+
 ALL_CHECKS = [
     check_table3_encode, check_enumeration_argmax, check_fig2_cuboctahedron, check_special_cases,
     check_invariants, check_ties_and_zeros, check_table3_pack, check_pack_layout, check_table3_delta,
     check_delta_identities, check_delta_one_bit_hamming, check_delta_bitwise, check_knn_bruteforce,
     check_knn_ties, check_knn_shard_merge, check_rerank_l2_order, check_rerank_invariants,
     check_masked_ternary_query_is_delta, check_masked_float_query, check_b158_worked, check_b158_properties,
+    check_knn_l2_worked, check_knn_l2_library_distance, check_knn_l2_equal_counts_is_delta,
 ]

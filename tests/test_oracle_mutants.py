@@ -19,6 +19,7 @@ MUTANTS = {
     7: "rerank ties go to the higher id",
     8: "masked addition ignores the sign",
     9: "b1.58 rounds ties away from zero",
+    10: "ternary distance counts differing coordinates",
 }
 
 
