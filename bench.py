@@ -115,6 +115,8 @@ def run_batching(tq, torch, db, queries, x, n, W, plain_qps, args, log):
     on_matrix = [i for i in range(nb) if batches[i][1] <= 128 and batches[i][0] >= 16]
 
     def timed(engine, which):
+        """HIP-event time of the scan launch(es) of each batch, in ms."""
+        per = []
         tq.tq_timing_read(1, reset=True)
         tq.tq_timing_enable(True)
         for i in which:
@@ -123,12 +125,15 @@ def run_batching(tq, torch, db, queries, x, n, W, plain_qps, args, log):
             tq.tq_encode(queries[q0:q0 + b], x, qc[:b])
             ids, sc = outs[k]
             tq.tq_search_knn(db, qc[:b], k, path=tq.TQ_PATH_BATCHED, engine=engine, ids=ids[:b], scores=sc[:b])
-        torch.cuda.synchronize()
+            ms, _ = tq.tq_timing_read(1, reset=True)
+            per.append(ms)
         tq.tq_timing_enable(False)
-        return tq.tq_timing_read(1, reset=True)
+        return per
 
-    kms_m, launches_m = timed(tq.TQ_ENGINE_MATRIX, on_matrix)
-    kms_p, launches_p = timed(tq.TQ_ENGINE_POPCOUNT, range(nb))
+    per_m = timed(tq.TQ_ENGINE_MATRIX, on_matrix)
+    per_p = timed(tq.TQ_ENGINE_POPCOUNT, range(nb))
+    kms_m, launches_m = sum(per_m), len(per_m)
+    kms_p, launches_p = sum(per_p), len(per_p)
     pairs_m = sum(batches[i][0] for i in on_matrix) * n
     pairs = sum(b for b, _ in batches[:nb]) * n
     flops = 2.0 * pairs_m * d_pad
@@ -137,6 +142,17 @@ def run_batching(tq, torch, db, queries, x, n, W, plain_qps, args, log):
     ops_per_pair = 5 * 4 * ((W + 3) // 4)
     valu_peak = 256 * 64 * 2.4e9 / 1e12
     tops = pairs * ops_per_pair / (kms_p * 1e-3) / 1e12
+    # The bound of each batch: one pass reads the whole database (HBM floor)
+    # and does 2 d_pad flops per pair (fp4 floor); a batch of b queries cannot
+    # finish before the larger of the two.  Sum of the floors over the sum of
+    # the measured times = the fraction of its own bound the mix reaches.
+    db_bytes = n * 8 * W
+    floor_m = [max(db_bytes / (HBM_PEAK_GBPS * 1e9), 2.0 * batches[i][0] * n * d_pad / (fp4_peak * 1e12)) * 1e3
+               for i in on_matrix]
+    hbm_bound_m = sum(1 for i in on_matrix
+                      if db_bytes / (HBM_PEAK_GBPS * 1e9) >= 2.0 * batches[i][0] * n * d_pad / (fp4_peak * 1e12))
+    floor_p = [max(db_bytes / (HBM_PEAK_GBPS * 1e9), batches[i][0] * n * ops_per_pair / (valu_peak * 1e12)) * 1e3
+               for i in range(nb)]
     # consistency: a few batches against the plain path
     ok = True
     for i in (0, 7, 123):
@@ -155,11 +171,15 @@ def run_batching(tq, torch, db, queries, x, n, W, plain_qps, args, log):
             "roofline": {"kernel": "scan_mfma_group_kernel (k <= 16) + scan_mfma_kernel", "bound": "mfma", "achieved": round(tflops, 1),
                          "peak": fp4_peak, "unit": "TFLOP/s", "frac": round(tflops / fp4_peak, 4),
                          "flops_per_pair": 2 * d_pad, "batches": len(on_matrix), "launches": launches_m,
-                         "avg_launch_ms": round(kms_m / max(1, launches_m), 4)},
+                         "avg_launch_ms": round(kms_m / max(1, launches_m), 4),
+                         "bound_ms": round(sum(floor_m), 3), "measured_ms": round(kms_m, 3),
+                         "frac_of_bound": round(sum(floor_m) / kms_m, 4), "hbm_bound_batches": hbm_bound_m},
             "roofline_popcount": {"kernel": "scan_batched_kernel", "bound": "alu", "achieved": round(tops, 2),
                                   "peak": round(valu_peak, 2), "unit": "Tops/s", "frac": round(tops / valu_peak, 4),
                                   "ops_per_pair": ops_per_pair, "batches": nb, "launches": launches_p,
-                                  "avg_launch_ms": round(kms_p / max(1, launches_p), 4)}}
+                                  "avg_launch_ms": round(kms_p / max(1, launches_p), 4),
+                                  "bound_ms": round(sum(floor_p), 3), "measured_ms": round(kms_p, 3),
+                                  "frac_of_bound": round(sum(floor_p) / kms_p, 4)}}
 
 
 def run_mid_sweep(tq, torch, args, log):
@@ -177,9 +197,18 @@ def run_mid_sweep(tq, torch, args, log):
     nrec = wl["recall_nq"]
     gt = metrics.ExactTopK(queries[:nrec], 10)
     codes = {x: torch.empty((n, 2 * W), dtype=torch.int32, device=dev) for x in xs}
+    # the encoders compared on the same vectors (Table 2 / Fig. 5: EVP at its
+    # default x, 1-bit = x = d, b1.58 absmean)
+    x_def = tq.tq_default_x(d)
+    enc_codes = {name: torch.empty((n, 2 * W), dtype=torch.int32, device=dev)
+                 for name in ("evp_default", "one_bit", "b158")}
     for r0, X in datagen.iter_rows(wl["spec"], datagen.DB, 0, n, dev):
+        m = X.shape[0]
         for x in xs:
-            tq.tq_encode(X, x, codes[x][r0:r0 + X.shape[0]])
+            tq.tq_encode(X, x, codes[x][r0:r0 + m])
+        tq.tq_encode(X, x_def, enc_codes["evp_default"][r0:r0 + m])
+        tq.tq_encode(X, d, enc_codes["one_bit"][r0:r0 + m])
+        tq.tq_encode_b158(X, enc_codes["b158"][r0:r0 + m])
         gt.add(X, r0)
     tq.tq_sync()
     gt_ids, _ = gt.result()
@@ -213,6 +242,29 @@ def run_mid_sweep(tq, torch, args, log):
         log(f"mid x={x}: recall@10 {row['recall_at_10']}, 10@100 {row['recall_10_at_100']}, "
             f"{row['qps']} q/s at k={k} ({row['scan_ms_per_query']} ms of scan kernels per query)")
         db.destroy()
+    # encoders on the same vectors: recall of the proxy top-10 / top-100
+    qr = queries[:nrec]
+    enc = []
+    for name, label, x_db, q_codes, metric in (
+            ("evp_default", f"EVP {{{x_def},{d}}} (default x), Delta", x_def, tq.tq_encode(qr, x_def),
+             tq.TQ_METRIC_DELTA),
+            ("one_bit", f"1-bit (x = d = {d}), Delta", d, tq.tq_encode(qr, d), tq.TQ_METRIC_DELTA),
+            ("b158", "b1.58 absmean, l2 between ternary vectors (2 Delta - nnz(v))", 0, tq.tq_encode_b158(qr),
+             tq.TQ_METRIC_L2),
+            ("b158", "b1.58 absmean, raw Delta (no norm correction)", 0, None, tq.TQ_METRIC_DELTA)):
+        if q_codes is None:
+            q_codes = tq.tq_encode_b158(qr)
+        db = tq.tq_db_create(enc_codes[name], d, x_db)
+        i10, _ = tq.tq_search_knn(db, q_codes, 10, path=tq.TQ_PATH_PLAIN, metric=metric)
+        i100, _ = tq.tq_search_knn(db, q_codes, 100, path=tq.TQ_PATH_PLAIN, metric=metric)
+        torch.cuda.synchronize()
+        row = {"encoder": label, "recall_at_10": round(metrics.recall_at(gt_ids, i10.cpu().numpy(), 10, 10), 4),
+               "recall_10_at_100": round(metrics.recall_at(gt_ids, i100.cpu().numpy(), 10, 100), 4)}
+        enc.append(row)
+        log(f"mid encoders: {label}: recall@10 {row['recall_at_10']}, 10@100 {row['recall_10_at_100']}")
+        db.destroy()
+    out["encoders"] = enc
+    del enc_codes
     torch.cuda.empty_cache()
     return out
 
@@ -476,6 +528,7 @@ def main():
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
+    sclk_before = tq.tq_clock_mhz()
     tq.tq_timing_read(0, reset=True)
     tq.tq_timing_read(1, reset=True)
     tq.tq_timing_enable(True)
@@ -607,6 +660,10 @@ def main():
 
     if not args.no_batching and args.workload == "large":
         result["batched"] = run_batching(tq, torch, db, queries, x, n, W, qps, args, log)
+    # the shader clock under load (device counters), before the timed steps
+    # and now; the vector-ALU and matrix-core peaks above assume 2 400 MHz
+    result["sclk_mhz"] = {"before_steps": round(sclk_before, 1), "after_batching": round(tq.tq_clock_mhz(), 1),
+                          "peak_assumed": 2400.0}
 
     # ---- CPU oracle on a bounded sample (rank 0, N=1 only)
     if cpu_rows:

@@ -192,8 +192,25 @@ typedef struct tq_search_opts {
                         TQ_ENGINE_POPCOUNT or TQ_ENGINE_MATRIX, or
                         TQ_ENGINE_SPARSE (plain path; AUTO path means plain);
                         results are identical */
-  int reserved[2];
+  int metric;        /* enum tq_metric (0 = TQ_METRIC_DELTA) */
+  int reserved[1];
 } tq_search_opts;
+
+/* What "nearest" means.  TQ_METRIC_DELTA: the largest Delta, the scalar
+ * product of the ternary vectors (Sec. 5.1.2) -- a distance proxy when every
+ * code has the same number of non-zeros, as {x,d} EVP codes do (Sec. 1.1:
+ * for vectors of equal norm the scalar product orders them by l2 distance).
+ * TQ_METRIC_L2: the smallest euclidean distance between the ternary vectors,
+ * the proxy a database of codes with varying non-zero counts needs (b1.58,
+ * Sec. 4.3; x = 0 databases); the reported score is
+ * 2 Delta - nnz(v) = nnz(q) - |q - v|^2 (larger = nearer; the squared
+ * distance is nnz(q) - score), same tie rule.  TQ_METRIC_L2 runs on the
+ * bit planes (plain path, and the popcount engine of the batched path);
+ * TQ_ENGINE_MATRIX or TQ_ENGINE_SPARSE with it is TQ_ERR_INVALID. */
+enum tq_metric {
+  TQ_METRIC_DELTA = 0,
+  TQ_METRIC_L2 = 1
+};
 
 enum tq_engine {
   TQ_ENGINE_AUTO = 0,     /* the tuned / default choice */
@@ -319,7 +336,12 @@ typedef struct tq_serve_cfg {
   int n_segments;        /* database segments per pass (a request needs one
                             tick per segment); 0 = one per 16M vectors */
   int max_request_nq;    /* largest nq of one request; 0 = 1024 */
-  int reserved[4];
+  int tick_timeout_us;   /* watchdog: a tick whose GPU work has not finished
+                            this many microseconds after it was queued stops
+                            the server; its requests then report
+                            TQ_ERR_DEVICE.  0 = no watchdog (the loop waits on
+                            the GPU without polling) */
+  int reserved[3];
 } tq_serve_cfg;
 
 typedef struct tq_req_stats {
@@ -370,6 +392,25 @@ int tq_serve_destroy(tq_server *srv);
 /* ---------------------------------------------------------------------- */
 /* Measurement                                                              */
 /* ---------------------------------------------------------------------- */
+
+/* The shader clock of the current device in MHz, measured while every compute
+ * unit runs a chain of dependent vector instructions (the ratio of the
+ * shader-clock and real-time counters read on the device).  Peaks quoted per
+ * clock (vector ALU, matrix cores) scale with it.  Waits for `stream`. */
+int tq_clock_mhz(double *mhz, void *stream);
+
+/* Upper bound on the device memory the library holds at once -- resident
+ * databases, search scratch, batched-path buffers and graphs' buffers,
+ * servers -- in bytes; 0 (the default) means none.  An allocation that would
+ * take the total past the bound fails as if the GPU were out of memory: the
+ * call returns TQ_ERR_NOMEM (tq_db_create, tq_serve_create, searches that
+ * need new scratch) and leaves nothing half-built.  Memory already held is
+ * not released.  For processes that share a GPU, and for exercising the
+ * out-of-memory paths in tests.  Process-wide, all devices together. */
+int tq_set_device_limit(uint64_t bytes);
+
+/* Device bytes the library holds at the moment (counted as for the limit). */
+int tq_device_bytes(uint64_t *held);
 
 /* Turn per-launch timing of the library's scan kernels on (1) or off (0).
  * When on, each scan launch is bracketed by HIP events on its own stream. */

@@ -76,8 +76,8 @@ int device_ctx(int dev, DevCtx **out) {
     int cu = 0;
     hipError_t e = hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
-    e = hipMalloc(&c.flags, 256);
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc(flags)");
+    e = dev_malloc(&c.flags, 256);
+    if (e != hipSuccess) return hip_fail(e, "device allocation (flags)");
     e = hipMemset(c.flags, 0, 256);
     if (e != hipSuccess) return hip_fail(e, "hipMemset(flags)");
     c.num_cu = cu;
@@ -141,6 +141,47 @@ TimedLaunch::~TimedLaunch() {
 }
 
 // ---------------------------------------------------------------------------
+// counted device allocations
+// ---------------------------------------------------------------------------
+
+namespace {
+struct DevMem {
+  std::mutex mu;
+  std::unordered_map<void *, size_t> sizes;
+  uint64_t held = 0;
+  uint64_t limit = 0;  // 0: none
+};
+DevMem g_mem;
+}  // namespace
+
+hipError_t dev_malloc_raw(void **p, size_t bytes) {
+  *p = nullptr;
+  std::lock_guard<std::mutex> g(g_mem.mu);
+  if (g_mem.limit && g_mem.held + bytes > g_mem.limit) return hipErrorOutOfMemory;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return e;
+  }
+  g_mem.sizes[*p] = bytes;
+  g_mem.held += bytes;
+  return hipSuccess;
+}
+
+void dev_free(void *p) {
+  if (!p) return;
+  {
+    std::lock_guard<std::mutex> g(g_mem.mu);
+    auto it = g_mem.sizes.find(p);
+    if (it != g_mem.sizes.end()) {
+      g_mem.held -= it->second;
+      g_mem.sizes.erase(it);
+    }
+  }
+  (void)hipFree(p);
+}
+
+// ---------------------------------------------------------------------------
 // scratch buffers
 // ---------------------------------------------------------------------------
 
@@ -149,14 +190,14 @@ int scratch_get(ScratchMap &map, hipStream_t s, size_t bytes, void **out) {
   if (sc.bytes < bytes) {
     if (sc.p) {
       (void)hipStreamSynchronize(s);
-      (void)hipFree(sc.p);
+      dev_free(sc.p);
       sc.p = nullptr;
       sc.bytes = 0;
     }
-    hipError_t e = hipMalloc(&sc.p, bytes);
+    hipError_t e = dev_malloc(&sc.p, bytes);
     if (e != hipSuccess) {
       sc.p = nullptr;
-      return hip_fail(e, "hipMalloc(scratch)");
+      return hip_fail(e, "device allocation (scratch)");
     }
     sc.bytes = bytes;
   }
@@ -166,7 +207,7 @@ int scratch_get(ScratchMap &map, hipStream_t s, size_t bytes, void **out) {
 
 void scratch_free_all(ScratchMap &map) {
   for (auto &kv : map)
-    if (kv.second.p) (void)hipFree(kv.second.p);
+    if (kv.second.p) dev_free(kv.second.p);
   map.clear();
 }
 
@@ -176,14 +217,14 @@ void scratch_free_all(ScratchMap &map) {
 
 int count_bad_codes(const uint32_t *codes, int64_t n, int d, int x, hipStream_t s, unsigned long long *bad) {
   unsigned long long *dcount = nullptr;
-  hipError_t e = hipMalloc(&dcount, sizeof *dcount);
-  if (e != hipSuccess) return hip_fail(e, "hipMalloc(counter)");
+  hipError_t e = dev_malloc(&dcount, sizeof *dcount);
+  if (e != hipSuccess) return hip_fail(e, "device allocation (counter)");
   unsigned long long h = 0;
   e = hipMemcpyAsync(dcount, &h, sizeof h, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = tqi::validate_launch(codes, n, d, x, dcount, s);
   if (e == hipSuccess) e = hipMemcpyAsync(&h, dcount, sizeof h, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(dcount);
+  dev_free(dcount);
   if (e != hipSuccess) return hip_fail(e, "code validation");
   *bad = h;
   return TQ_OK;
@@ -309,15 +350,15 @@ int tq_db_create(const uint32_t *codes, int64_t n, int d, int x, void *stream, t
   const int64_t ntiles = (n + tqi::kTileVecs - 1) / tqi::kTileVecs;
   db->bytes = static_cast<size_t>(ntiles) * 2 * nc * 64 * sizeof(uint4);
   uint4 *tiles = nullptr;
-  hipError_t e = hipMalloc(&tiles, db->bytes);
+  hipError_t e = dev_malloc(&tiles, db->bytes);
   if (e != hipSuccess) {
     delete db;
-    return hip_fail(e, "hipMalloc(database)");
+    return hip_fail(e, "device allocation (database)");
   }
   e = tqi::repack_launch(codes, n, d, tiles, ntiles, nc, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
-    (void)hipFree(tiles);
+    dev_free(tiles);
     delete db;
     return hip_fail(e, "database repack");
   }
@@ -326,14 +367,14 @@ int tq_db_create(const uint32_t *codes, int64_t n, int d, int x, void *stream, t
   if (sc > 0) {
     const size_t sbytes = static_cast<size_t>(ntiles) * sc * 64 * sizeof(uint4);
     uint4 *sp = nullptr;
-    e = hipMalloc(&sp, sbytes);
+    e = dev_malloc(&sp, sbytes);
     if (e == hipSuccess) {
       e = tqi::sparse_repack_launch(db->dev, sp, sc, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
-      if (e != hipSuccess) (void)hipFree(sp);
+      if (e != hipSuccess) dev_free(sp);
     }
     if (e != hipSuccess) {
-      (void)hipFree(tiles);
+      dev_free(tiles);
       delete db;
       return hip_fail(e, "index-list copy of the database");
     }
@@ -372,8 +413,8 @@ int tq_db_destroy(tq_db *db) {
     std::lock_guard<std::mutex> l(db->mu);
     scratch_free_all(db->scratch);
     batched_release(db);
-    if (db->dev.tiles) (void)hipFree(const_cast<uint4 *>(db->dev.tiles));
-    if (db->dev.sparse) (void)hipFree(const_cast<uint4 *>(db->dev.sparse));
+    if (db->dev.tiles) dev_free(const_cast<uint4 *>(db->dev.tiles));
+    if (db->dev.sparse) dev_free(const_cast<uint4 *>(db->dev.sparse));
   }
   delete db;
   return TQ_OK;
@@ -393,6 +434,10 @@ int tq_search_knn(const tq_db *cdb, const uint32_t *qcodes, int nq, int k, int32
   if (opts && (opts->grid < 0 || opts->qtile < 0)) return fail(TQ_ERR_INVALID, "negative grid or qtile");
   const int engine = opts ? opts->engine : TQ_ENGINE_AUTO;
   if (engine < TQ_ENGINE_AUTO || engine > TQ_ENGINE_SPARSE) return fail(TQ_ERR_INVALID, "unknown engine %d", engine);
+  const int metric = opts ? opts->metric : TQ_METRIC_DELTA;
+  if (metric != TQ_METRIC_DELTA && metric != TQ_METRIC_L2) return fail(TQ_ERR_INVALID, "unknown metric %d", metric);
+  if (metric == TQ_METRIC_L2 && (engine == TQ_ENGINE_MATRIX || engine == TQ_ENGINE_SPARSE))
+    return fail(TQ_ERR_INVALID, "metric L2 runs on the bit planes: engine AUTO or POPCOUNT (engine %d given)", engine);
   if (engine == TQ_ENGINE_SPARSE) {
     if (path == TQ_PATH_BATCHED) return fail(TQ_ERR_INVALID, "the index-list engine serves the plain path only");
     if (!db->dev.sparse)
@@ -411,7 +456,7 @@ int tq_search_knn(const tq_db *cdb, const uint32_t *qcodes, int nq, int k, int32
   std::lock_guard<std::mutex> l(db->mu);
   const int use = engine == TQ_ENGINE_SPARSE ? TQ_PATH_PLAIN : choose_path(db, path, nq, k);
   if (use == TQ_PATH_BATCHED) return search_batched(db, qcodes, nq, k, ids, scores, opts, s);
-  return search_plain(db, qcodes, nq, k, ids, scores, opts ? opts->grid : 0, engine, s);
+  return search_plain(db, qcodes, nq, k, ids, scores, opts ? opts->grid : 0, engine, s, nullptr, metric);
 }
 
 int tq_search_masked(const tq_db *cdb, const float *Q, int nq, int k, int32_t *ids, float *scores,
@@ -464,6 +509,21 @@ int tq_autotune(const tq_db *cdb, int nq_max, const int *ks, int nks, void *stre
   DeviceGuard g(db->device);
   std::lock_guard<std::mutex> l(db->mu);
   return autotune(db, nq_max, ks, nks, static_cast<hipStream_t>(stream), log_level() >= 2);
+}
+
+int tq_set_device_limit(uint64_t bytes) {
+  clear_error();
+  std::lock_guard<std::mutex> g(g_mem.mu);
+  g_mem.limit = bytes;
+  return TQ_OK;
+}
+
+int tq_device_bytes(uint64_t *held) {
+  clear_error();
+  if (!held) return fail(TQ_ERR_INVALID, "null held");
+  std::lock_guard<std::mutex> g(g_mem.mu);
+  *held = g_mem.held;
+  return TQ_OK;
 }
 
 int tq_timing_enable(int enable) {

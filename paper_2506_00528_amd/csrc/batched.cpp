@@ -206,11 +206,11 @@ void free_entry(BatchEntry &e) {
   }
   if (e.exec) (void)hipGraphExecDestroy(e.exec);
   if (e.graph) (void)hipGraphDestroy(e.graph);
-  if (e.qprep) (void)hipFree(e.qprep);
-  if (e.prm) (void)hipFree(e.prm);
-  if (e.partial) (void)hipFree(e.partial);
-  if (e.mid) (void)hipFree(e.mid);
-  if (e.bound) (void)hipFree(e.bound);
+  if (e.qprep) dev_free(e.qprep);
+  if (e.prm) dev_free(e.prm);
+  if (e.partial) dev_free(e.partial);
+  if (e.mid) dev_free(e.mid);
+  if (e.bound) dev_free(e.bound);
   e = BatchEntry{};
 }
 
@@ -235,17 +235,17 @@ int get_entry(tq_db *db, hipStream_t s, int bucket, int k, const Shape &sh, Batc
   // (query, part) lists: nq * parts <= qtile * grid + nq, plus up to 7 parts
   // per query from rounding the part count to a multiple of the XCD count
   const size_t lists = static_cast<size_t>(sh.qtile) * sh.grid + static_cast<size_t>(tqi::kXcds + 1) * bucket;
-  hipError_t err = hipMalloc(&e.qprep, qbytes);
-  if (err == hipSuccess) err = hipMalloc(&e.prm, sizeof(tqi::BatchParams));
-  if (err == hipSuccess) err = hipMalloc(&e.partial, lists * k * sizeof(uint64_t));
-  if (err == hipSuccess) err = hipMalloc(&e.bound, lists * tqi::kBoundSlotsPerPart * sizeof(uint64_t));
+  hipError_t err = dev_malloc(&e.qprep, qbytes);
+  if (err == hipSuccess) err = dev_malloc(&e.prm, sizeof(tqi::BatchParams));
+  if (err == hipSuccess) err = dev_malloc(&e.partial, lists * k * sizeof(uint64_t));
+  if (err == hipSuccess) err = dev_malloc(&e.bound, lists * tqi::kBoundSlotsPerPart * sizeof(uint64_t));
   if (err == hipSuccess) err = hipEventCreateWithFlags(&e.done, hipEventDisableTiming);
   if (err == hipSuccess)
-    err = hipMalloc(&e.mid, static_cast<size_t>(tqi::merge_batched_mid_keys(bucket, sh.grid + tqi::kXcds, k)) *
+    err = dev_malloc(&e.mid, static_cast<size_t>(tqi::merge_batched_mid_keys(bucket, sh.grid + tqi::kXcds, k)) *
                                 sizeof(uint64_t));
   if (err != hipSuccess) {
     free_entry(e);
-    return hip_fail(err, "hipMalloc(batched buffers)");
+    return hip_fail(err, "device allocation (batched buffers)");
   }
   *out = &(st.entries[key] = e);
   return TQ_OK;
@@ -294,16 +294,16 @@ int ensure_graph(tq_db *db, BatchEntry &e, int bucket, int k, const Shape &sh) {
   return TQ_OK;
 }
 
-// One chunk of <= kMaxBucket queries.
+// One chunk of <= kMaxBucket queries; l2 != 0 scores 2 Delta - nnz(v).
 int run_chunk_on(tq_db *db, BatchEntry *e, const uint32_t *qcodes, int nq, int k, int32_t *ids, int32_t *scores,
-                 const Shape &sh, bool use_graph, hipStream_t s);
+                 const Shape &sh, bool use_graph, hipStream_t s, int l2);
 
 int run_chunk(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids, int32_t *scores, const Shape &sh,
-              bool use_graph, hipStream_t s) {
+              bool use_graph, hipStream_t s, int l2 = 0) {
   BatchEntry *e = nullptr;
   int rc = get_entry(db, s, bucket_of(nq), k, sh, &e);
   if (rc) return rc;
-  rc = run_chunk_on(db, e, qcodes, nq, k, ids, scores, sh, use_graph, s);
+  rc = run_chunk_on(db, e, qcodes, nq, k, ids, scores, sh, use_graph, s, l2);
   // the entry's latest use, for a later eviction
   e->last_use = ++db->batched->clock;
   if (hipEventRecord(e->done, s) != hipSuccess && rc == TQ_OK) rc = fail(TQ_ERR_DEVICE, "hipEventRecord");
@@ -311,11 +311,11 @@ int run_chunk(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids, in
 }
 
 int run_chunk_on(tq_db *db, BatchEntry *e, const uint32_t *qcodes, int nq, int k, int32_t *ids, int32_t *scores,
-                 const Shape &sh, bool use_graph, hipStream_t s) {
+                 const Shape &sh, bool use_graph, hipStream_t s, int l2) {
   const int bucket = bucket_of(nq);
   int rc = TQ_OK;
   hipError_t err = tqi::batch_prep_launch(qcodes, nq, bucket, db->dev, sh.qtile, sh.grid, ids, scores, e->qprep,
-                                          e->prm, e->bound, s);
+                                          e->prm, e->bound, l2, s);
   if (err != hipSuccess) return hip_fail(err, "batch prep launch");
   if (timing_enabled()) {
     // timed runs launch directly so the events bracket the scan kernel alone
@@ -355,6 +355,8 @@ Shape shape_for(tq_db *db, int k, int bucket, const tq_search_opts *opts) {
   int engine = opts ? opts->engine : TQ_ENGINE_AUTO;
   const int qtile = opts ? opts->qtile : 0;
   if (engine == TQ_ENGINE_AUTO && qtile > 0) engine = qtile >= 64 ? TQ_ENGINE_MATRIX : TQ_ENGINE_POPCOUNT;
+  // the l2 order (2 Delta - nnz(v)) is scored by the popcount engine only
+  if (engine == TQ_ENGINE_AUTO && opts && opts->metric == TQ_METRIC_L2) engine = TQ_ENGINE_POPCOUNT;
   bool changed = false;
   if (engine != TQ_ENGINE_AUTO && engine != sh.engine) {
     sh.engine = engine;
@@ -396,6 +398,8 @@ int search_batched(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *id
   if (engine < TQ_ENGINE_AUTO || engine > TQ_ENGINE_MATRIX)
     return fail(TQ_ERR_INVALID, "engine %d does not serve the batched path", engine);
   const bool matrix = engine == TQ_ENGINE_MATRIX || (engine == TQ_ENGINE_AUTO && q >= 64);
+  const int l2 = opts && opts->metric == TQ_METRIC_L2 ? 1 : 0;
+  if (matrix && l2) return fail(TQ_ERR_INVALID, "the matrix engine scores Delta only (metric L2 given)");
   if (matrix && tqi::rows_for_k(k) > 2) return fail(TQ_ERR_INVALID, "the matrix engine supports k <= 128 (k=%d)", k);
   if (q > 0) {
     if (matrix) {
@@ -413,7 +417,7 @@ int search_batched(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *id
     const int m = std::min(kMaxBucket, nq - q0);
     const Shape sh = shape_for(db, k, bucket_of(m), opts);
     int rc = run_chunk(db, qcodes + static_cast<int64_t>(q0) * row_words, m, k, ids + static_cast<int64_t>(q0) * k,
-                       scores + static_cast<int64_t>(q0) * k, sh, use_graph, s);
+                       scores + static_cast<int64_t>(q0) * k, sh, use_graph, s, l2);
     if (rc) return rc;
   }
   return TQ_OK;
@@ -520,11 +524,11 @@ int autotune(tq_db *db, int nq_max, const int *ks, int nks, hipStream_t s, int v
   int32_t *ids = nullptr, *scores = nullptr;
   const int W = db->dev.W;
   const size_t row_bytes = static_cast<size_t>(2 * W) * sizeof(uint32_t);
-  hipError_t err = hipMalloc(&q, static_cast<size_t>(maxb) * row_bytes);
+  hipError_t err = dev_malloc(&q, static_cast<size_t>(maxb) * row_bytes);
   int kmax = 1;
   for (int i = 0; i < nks; ++i) kmax = std::max(kmax, ks[i]);
-  if (err == hipSuccess) err = hipMalloc(&ids, static_cast<size_t>(maxb) * kmax * sizeof(int32_t));
-  if (err == hipSuccess) err = hipMalloc(&scores, static_cast<size_t>(maxb) * kmax * sizeof(int32_t));
+  if (err == hipSuccess) err = dev_malloc(&ids, static_cast<size_t>(maxb) * kmax * sizeof(int32_t));
+  if (err == hipSuccess) err = dev_malloc(&scores, static_cast<size_t>(maxb) * kmax * sizeof(int32_t));
   tqi::DbDev head = db->dev;
   head.n = nqq;
   head.ntiles = (nqq + 63) / 64;
@@ -603,9 +607,9 @@ int autotune(tq_db *db, int nq_max, const int *ks, int nks, hipStream_t s, int v
     }
   }
   (void)hipStreamSynchronize(s);
-  if (q) (void)hipFree(q);
-  if (ids) (void)hipFree(ids);
-  if (scores) (void)hipFree(scores);
+  if (q) dev_free(q);
+  if (ids) dev_free(ids);
+  if (scores) dev_free(scores);
   return rc;
 }
 

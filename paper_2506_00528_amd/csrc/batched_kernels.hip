@@ -45,7 +45,8 @@ __global__ __launch_bounds__(256) void prep_rows_kernel(const uint32_t *__restri
 __global__ __launch_bounds__(256) void batch_prep_kernel(const uint32_t *__restrict__ qcodes, int nq, int bucket,
                                                          int W, int nc, int qtile, int grid, int64_t ntiles,
                                                          int32_t *ids, int32_t *scores, uint32_t *__restrict__ qprep,
-                                                         BatchParams *__restrict__ prm, uint64_t *__restrict__ bound) {
+                                                         BatchParams *__restrict__ prm, uint64_t *__restrict__ bound,
+                                                         int l2) {
   const int W4 = 4 * nc;
   const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (bound) {
@@ -73,6 +74,7 @@ __global__ __launch_bounds__(256) void batch_prep_kernel(const uint32_t *__restr
     b.ids = ids;
     b.scores = scores;
     b.bound = bound;
+    b.l2 = l2;
     *prm = b;
   }
 }
@@ -118,6 +120,8 @@ __global__ __launch_bounds__(kBatchBlock) void scan_batched_kernel(const uint4 *
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int nq = prm->nq, nqt = prm->nqt, parts = prm->parts;
+  // score = Delta * mul - sub: Delta, or 2 Delta - nnz(v) for the l2 order
+  const int32_t mul = prm->l2 ? 2 : 1;
   uint64_t *const lb = lbs + wave * QT;
   const int64_t tpp = prm->tiles_per_part;
   const int64_t tile_lo = prm->tile_lo, tile_hi = prm->tile_hi;
@@ -195,6 +199,7 @@ __global__ __launch_bounds__(kBatchBlock) void scan_batched_kernel(const uint4 *
       }
       const int64_t id = t * 64 + lane;
       const bool ok = id < n;
+      const int32_t sub = mul == 2 ? vec_nnz<NC>(vz) : 0;
 #pragma unroll
       for (int qi = 0; qi < QT; ++qi) {
         if (qi < nact) {
@@ -207,7 +212,7 @@ __global__ __launch_bounds__(kBatchBlock) void scan_batched_kernel(const uint4 *
             delta_word(a, qw[4 * c + 2], qw[4 * NC + 4 * c + 2], vz[c].z, vg[c].z);
             delta_word(a, qw[4 * c + 3], qw[4 * NC + 4 * c + 3], vz[c].w, vg[c].w);
           }
-          const uint64_t key = make_key(delta_value(a), static_cast<uint32_t>(id));
+          const uint64_t key = make_key(delta_value(a) * mul - sub, static_cast<uint32_t>(id));
           offer_keys<R>(list[qi], thr[qi], key, ok, km1, prune ? lb[qi] : 0ull);
         }
       }
@@ -278,11 +283,11 @@ int batched_max_qtile(int k) {
 
 hipError_t batch_prep_launch(const uint32_t *qcodes, int nq, int bucket, const DbDev &db, int qtile, int grid,
                              int32_t *ids, int32_t *scores, uint32_t *qprep, BatchParams *prm, uint64_t *bound,
-                             hipStream_t s) {
+                             int l2, hipStream_t s) {
   const int64_t threads = static_cast<int64_t>(bucket) * 4 * db.nc;
   const unsigned blocks = static_cast<unsigned>((threads + 255) / 256);
   hipLaunchKernelGGL(batch_prep_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, qcodes, nq, bucket, db.W,
-                     db.nc, qtile, grid, db.ntiles, ids, scores, qprep, prm, bound);
+                     db.nc, qtile, grid, db.ntiles, ids, scores, qprep, prm, bound, l2);
   return hipGetLastError();
 }
 

@@ -61,6 +61,8 @@ extern "C" int tq_search_knn_noalloc(const tq_db *cdb, const uint32_t *qcodes, i
   const int engine = opts ? opts->engine : TQ_ENGINE_AUTO;
   if (engine != TQ_ENGINE_AUTO && engine != TQ_ENGINE_POPCOUNT && engine != TQ_ENGINE_SPARSE)
     return fail(TQ_ERR_INVALID, "engine %d: the plain path takes AUTO, POPCOUNT or SPARSE", engine);
+  const int metric = opts ? opts->metric : TQ_METRIC_DELTA;
+  if (metric != TQ_METRIC_DELTA && metric != TQ_METRIC_L2) return fail(TQ_ERR_INVALID, "unknown metric %d", metric);
   if (engine == TQ_ENGINE_SPARSE && !db->dev.sparse)
     return fail(TQ_ERR_INVALID, "no index-list copy: kept only for 8x <= d (x=%d, d=%d)", db->dev.x, db->dev.d);
   if (db->device < 0 || db->device >= kMaxDevices) return fail(TQ_ERR_DEVICE, "device index %d", db->device);
@@ -73,5 +75,5 @@ extern "C" int tq_search_knn_noalloc(const tq_db *cdb, const uint32_t *qcodes, i
   // overlaps (other streams of the same device) still share the one array.
   std::lock_guard<std::mutex> l(g_mu);
   return search_plain(db, qcodes, nq, k, ids, scores, opts ? opts->grid : 0, engine,
-                      static_cast<hipStream_t>(stream), &span);
+                      static_cast<hipStream_t>(stream), &span, metric);
 }

@@ -20,6 +20,7 @@ constexpr int kScanWaves = 4;
 constexpr int kScanBlock = 64 * kScanWaves;
 
 // `tstride` > 1 scans only every tstride-th tile (a sample of the database).
+// `l2` != 0 scores 2 Delta - nnz(v) instead of Delta.
 // With `floor_at` (the result row of a sample scan of this query, k ids then
 // k scores), keys below the sample's k-th key are dropped from the start: the
 // k-th key of a subset is never above the k-th key of the whole database.
@@ -29,7 +30,7 @@ __global__ __launch_bounds__(kScanBlock, 2) void scan_plain_kernel(const uint4 *
                                                                const uint32_t *__restrict__ qcode, int k,
                                                                uint64_t *__restrict__ partial, int tstride,
                                                                const int32_t *__restrict__ floor_ids,
-                                                               const int32_t *__restrict__ floor_scores) {
+                                                               const int32_t *__restrict__ floor_scores, int l2) {
   __shared__ uint64_t lds[2][kScanWaves * 64 * R];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -51,7 +52,8 @@ __global__ __launch_bounds__(kScanBlock, 2) void scan_plain_kernel(const uint4 *
   // one is scored (past the end a wave re-reads the last tile, so the loads
   // need no branch).
   auto score = [&](const TileVec<NC> &v, int64_t t) {
-    const int32_t delta = vec_delta<NC>(v, q);
+    int32_t delta = vec_delta<NC>(v, q);
+    if (l2) delta = 2 * delta - vec_nnz<NC>(v.vz);
     const int64_t id = t * tstride * 64 + lane;
     offer_keys<R>(list, thr, make_key(delta, static_cast<uint32_t>(id)), id < n, km1, floor);
   };
@@ -185,7 +187,7 @@ template <int NC, int R>
 hipError_t scan_nc_r(const DbDev &db, const uint32_t *qcode, int k, int grid, uint64_t *partial,
                      const PlainScanOpts &o, hipStream_t s) {
   hipLaunchKernelGGL((scan_plain_kernel<NC, R>), dim3(grid), dim3(kScanBlock), 0, s, db.tiles, db.n,
-                     db.ntiles, db.W, qcode, k, partial, o.tstride, o.floor_ids, o.floor_scores);
+                     db.ntiles, db.W, qcode, k, partial, o.tstride, o.floor_ids, o.floor_scores, o.l2);
   return hipGetLastError();
 }
 

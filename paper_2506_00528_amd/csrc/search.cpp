@@ -41,8 +41,11 @@ static int default_sparse_grid(const tq_db *db) {
 }
 
 int search_plain(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids, int32_t *scores, int grid,
-                 int engine, hipStream_t s, const ScratchSpan *ext) {
-  const bool sparse = engine == TQ_ENGINE_SPARSE || (engine == TQ_ENGINE_AUTO && tqi::sparse_preferred(db->dev));
+                 int engine, hipStream_t s, const ScratchSpan *ext, int metric) {
+  const int l2 = metric == TQ_METRIC_L2 ? 1 : 0;
+  if (l2 && engine == TQ_ENGINE_SPARSE) return fail(TQ_ERR_INVALID, "the index-list engine scores Delta only");
+  const bool sparse =
+      engine == TQ_ENGINE_SPARSE || (engine == TQ_ENGINE_AUTO && !l2 && tqi::sparse_preferred(db->dev));
   if (sparse && !db->dev.sparse) return fail(TQ_ERR_INVALID, "no index-list copy of this database");
   const int G = grid > 0 ? grid : sparse ? default_sparse_grid(db) : default_plain_grid(db);
   // Large k against the vectors a wave scans: each wave keeps k keys of its
@@ -84,6 +87,7 @@ int search_plain(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids,
     if (sampled) {
       tqi::PlainScanOpts o;
       o.tstride = kSampleStride;
+      o.l2 = l2;
       for (int i = 0; i < nc; ++i) {
         TimedLaunch t(kTimePlain, s, timed);
         hipError_t e = tqi::scan_plain_launch(db->dev, qcodes + static_cast<int64_t>(q0 + i) * row_words, k, G,
@@ -98,6 +102,7 @@ int search_plain(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids,
       const uint32_t *qc = qcodes + static_cast<int64_t>(q0 + i) * row_words;
       uint64_t *dst = partial + static_cast<size_t>(i) * G * k;
       tqi::PlainScanOpts o;
+      o.l2 = l2;
       if (sampled) {
         o.floor_ids = smp_ids + static_cast<size_t>(i) * k;
         o.floor_scores = smp_scores + static_cast<size_t>(i) * k;

@@ -27,6 +27,7 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <mutex>
@@ -61,6 +62,7 @@ struct Request {
   int ticks_done = 0;
   size_t bytes = 0;
   hipEvent_t done = nullptr;  // results are on the host once it fires
+  uint64_t last_tick_ns = 0;  // when its last tick was queued (watchdog)
 };
 
 // Pinned, host-to-device staged parameters of one tick: BatchParams followed
@@ -70,6 +72,7 @@ struct TickStage {
   hipEvent_t consumed = nullptr;  // the copy out of `host` has executed
   hipEvent_t done = nullptr;      // all of the tick's device work has executed
   bool used = false;
+  uint64_t queued_ns = 0;         // when the tick was queued (watchdog)
 };
 
 constexpr int kStages = 4;
@@ -120,6 +123,7 @@ struct tq_server {
   std::atomic<uint64_t> n_ticks{0};
   bool stopping = false;
   int loop_error = TQ_OK;
+  char loop_msg[160] = "";  // why the loop stopped
   std::thread th;
   int64_t tick = 0;
 };
@@ -260,7 +264,10 @@ void collect_finished_locked(tq_server *s, std::vector<Request *> &finishing, bo
       ++i;
       continue;
     }
-    if (q != hipSuccess) s->loop_error = TQ_ERR_DEVICE;
+    if (q != hipSuccess) {
+      s->loop_error = TQ_ERR_DEVICE;
+      std::snprintf(s->loop_msg, sizeof s->loop_msg, "device error: %s", hipGetErrorString(q));
+    }
     const uint64_t t = now_ns();
     r->ids.resize(static_cast<size_t>(r->nq) * r->k);
     r->scores.resize(r->ids.size());
@@ -284,6 +291,31 @@ void collect_finished_locked(tq_server *s, std::vector<Request *> &finishing, bo
     finishing.pop_back();
   }
   s->cv_done.notify_all();
+}
+
+// Waits for `ev`.  Without a watchdog this blocks in the runtime; with one it
+// polls and gives up once `queued_ns` + the timeout has passed, returning
+// hipErrorNotReady (the event's state at that moment).  The GPU work itself is left to finish: the caller stops the loop
+// and the drain waits for the stream.
+hipError_t wait_tick(const tq_server *s, hipEvent_t ev, uint64_t queued_ns) {
+  if (s->cfg.tick_timeout_us <= 0) return hipEventSynchronize(ev);
+  const uint64_t deadline = queued_ns + static_cast<uint64_t>(s->cfg.tick_timeout_us) * 1000ull;
+  for (;;) {
+    const hipError_t q = hipEventQuery(ev);
+    if (q != hipErrorNotReady) return q;
+    if (now_ns() > deadline) return hipErrorNotReady;
+    std::this_thread::sleep_for(std::chrono::microseconds(20));
+  }
+}
+
+void stop_loop_locked(tq_server *s, hipError_t e) {
+  s->loop_error = TQ_ERR_DEVICE;
+  if (e == hipErrorNotReady)
+    std::snprintf(s->loop_msg, sizeof s->loop_msg, "tick watchdog: a tick was not done %d us after it was queued",
+                  s->cfg.tick_timeout_us);
+  else
+    std::snprintf(s->loop_msg, sizeof s->loop_msg, "device error: %s", hipGetErrorString(e));
+  s->stopping = true;
 }
 
 void serve_loop(tq_server *s) {
@@ -327,8 +359,12 @@ void serve_loop(tq_server *s) {
     if (s->active.empty()) {
       if (!finishing.empty()) {
         lk.unlock();
-        (void)hipEventSynchronize(finishing.front()->done);
+        const hipError_t we = wait_tick(s, finishing.front()->done, finishing.front()->last_tick_ns);
         lk.lock();
+        if (we != hipSuccess) {  // in-flight requests report it from poll / wait
+          stop_loop_locked(s, we);
+          break;
+        }
         collect_finished_locked(s, finishing, false);
         continue;
       }
@@ -347,16 +383,18 @@ void serve_loop(tq_server *s) {
     }
     const int cur = s->next_stage;
     s->next_stage = (cur + 1) % kStages;
+    const uint64_t queued = now_ns();
+    for (Request *r : plan.retiring) r->last_tick_ns = queued;
     lk.unlock();
+    s->stage[cur].queued_ns = queued;
     hipError_t e = enqueue_tick(s, plan, s->stage[cur]);
     // at most two ticks in flight: wait for the previous one before planning
     // the next (the GPU keeps working on this one meanwhile)
     TickStage &prev = s->stage[(cur + kStages - 1) % kStages];
-    if (e == hipSuccess && prev.used) e = hipEventSynchronize(prev.done);
+    if (e == hipSuccess && prev.used) e = wait_tick(s, prev.done, prev.queued_ns);
     lk.lock();
     if (e != hipSuccess) {  // requests in flight report the error from poll / wait
-      s->loop_error = TQ_ERR_DEVICE;
-      s->stopping = true;
+      stop_loop_locked(s, e);
       break;
     }
     s->tick++;
@@ -381,7 +419,7 @@ void free_server(tq_server *s) {
   if (s->stream) (void)hipStreamSynchronize(s->stream);
   for (void *p : {(void *)s->d_qcanon, (void *)s->d_qrows, (void *)s->d_qtick, (void *)s->d_running, (void *)s->d_partial,
                   (void *)s->d_mid, (void *)s->d_bound, (void *)s->d_tick, (void *)s->d_ids, (void *)s->d_scores})
-    if (p) (void)hipFree(p);
+    if (p) dev_free(p);
   for (void *p : {(void *)s->h_qcanon, (void *)s->h_ids, (void *)s->h_scores})
     if (p) (void)hipHostFree(p);
   for (auto &st : s->stage) {
@@ -417,6 +455,7 @@ int tq_serve_create(const tq_db *db, const tq_serve_cfg *cfg, tq_server **out) {
     return fail(TQ_ERR_INVALID, "max_k=%d outside [1, min(n, %d)]", c.max_k, TQ_MAX_K);
   if (c.max_request_nq < 1) return fail(TQ_ERR_INVALID, "max_request_nq=%d", c.max_request_nq);
   if (c.n_segments < 0) return fail(TQ_ERR_INVALID, "n_segments=%d", c.n_segments);
+  if (c.tick_timeout_us < 0) return fail(TQ_ERR_INVALID, "tick_timeout_us=%d", c.tick_timeout_us);
 
   tq_server *s = new (std::nothrow) tq_server();
   if (!s) return fail(TQ_ERR_NOMEM, "host allocation");
@@ -444,7 +483,7 @@ int tq_serve_create(const tq_db *db, const tq_serve_cfg *cfg, tq_server **out) {
   const size_t M = c.max_slots;
   hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
   auto dm = [&](void **p, size_t bytes) {
-    if (e == hipSuccess) e = hipMalloc(p, bytes);
+    if (e == hipSuccess) e = dev_malloc_raw(p, bytes);
   };
   auto hm = [&](void **p, size_t bytes) {
     if (e == hipSuccess) e = hipHostMalloc(p, bytes, hipHostMallocDefault);
@@ -552,7 +591,7 @@ int tq_serve_poll(tq_server *s, uint64_t ticket, int32_t *ids, int32_t *scores, 
                                                              (unsigned long long)ticket);
   Request *r = it->second;
   if (r->state != RState::Done) {
-    if (s->loop_error) return fail(s->loop_error, "the serve loop stopped after a device error");
+    if (s->loop_error) return fail(s->loop_error, "the serve loop stopped: %s", s->loop_msg);
     return TQ_ERR_AGAIN;
   }
   return collect_locked(s, r, ids, scores, st);
@@ -569,7 +608,7 @@ int tq_serve_wait(tq_server *s, uint64_t ticket, int timeout_ms, int32_t *ids, i
       return fail(TQ_ERR_NOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
     Request *r = it->second;
     if (r->state == RState::Done) return collect_locked(s, r, ids, scores, st);
-    if (s->loop_error) return fail(s->loop_error, "the serve loop stopped after a device error");
+    if (s->loop_error) return fail(s->loop_error, "the serve loop stopped: %s", s->loop_msg);
     if (timeout_ms < 0) {
       s->cv_done.wait(lk);
     } else if (s->cv_done.wait_until(lk, deadline) == std::cv_status::timeout) {

@@ -13,7 +13,7 @@ struct BatchParams {
   int nq;                  // real queries of the call (<= bucket)
   int nqt;                 // query tiles: ceil(nq / qtile)
   int parts;               // database parts: the grid gets nqt * parts work items
-  int pad;
+  int l2;                  // 1: score 2 Delta - nnz(v) (TQ_METRIC_L2), 0: Delta
   int64_t tiles_per_part;  // 64-vector tiles per part
   int64_t tile_lo;         // database tiles scanned: [tile_lo, tile_hi)
   int64_t tile_hi;
@@ -62,7 +62,7 @@ __host__ __device__ inline void batch_split(BatchParams &b, int nq, int qtile, i
   if (parts < 1) parts = 1;
   parts = (parts + kXcds - 1) / kXcds * kXcds;
   b.parts = static_cast<int>(parts);
-  b.pad = 0;
+  b.l2 = 0;
   b.running_stride = 0;
   b.tiles_per_part = (ntiles + parts - 1) / parts;
   b.tile_lo = lo;
@@ -74,9 +74,10 @@ int batched_max_qtile(int k);
 
 // `bound` (may be null) holds at least nq * parts * kBoundSlotsPerPart keys;
 // the prep kernel zeroes them.
+// `l2` selects the score (BatchParams::l2).
 hipError_t batch_prep_launch(const uint32_t *qcodes, int nq, int bucket, const DbDev &db, int qtile, int grid,
                              int32_t *ids, int32_t *scores, uint32_t *qprep, BatchParams *prm, uint64_t *bound,
-                             hipStream_t s);
+                             int l2, hipStream_t s);
 hipError_t scan_batched_launch(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile,
                                int grid, uint64_t *partial, hipStream_t s);
 // The same scan on the fp4 matrix cores (mfma_kernels.hip): k <= 128 with

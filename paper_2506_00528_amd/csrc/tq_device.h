@@ -87,6 +87,17 @@ __device__ __forceinline__ int32_t vec_delta(const TileVec<NC> &v, const QueryWo
   return delta_value(a);
 }
 
+// Non-zeros of this lane's vector (popcount of its nz plane): with it,
+// 2 Delta - nnz(v) = nnz(q) - |q - v|^2 orders ternary vectors of varying
+// non-zero counts by euclidean distance.
+template <int NC>
+__device__ __forceinline__ int32_t vec_nnz(const u32x4 (&vz)[NC]) {
+  uint32_t s = 0;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) s += __popc(vz[c].x) + __popc(vz[c].y) + __popc(vz[c].z) + __popc(vz[c].w);
+  return static_cast<int32_t>(s);
+}
+
 // Delta of the query against the 64 vectors of one tile (this lane's vector).
 template <int NC>
 __device__ __forceinline__ int32_t tile_delta(const uint4 *__restrict__ tile, int lane,

@@ -95,10 +95,13 @@ hipError_t validate_launch(const uint32_t *codes, int64_t n, int d, int x,
 // scans every tstride-th tile only (a sample); floor_ids / floor_scores (k
 // each: a sample scan's result row for this query, device) let the scan drop
 // keys below that row's k-th key.
+// l2 != 0 scores 2 Delta - nnz(v) (the euclidean order between ternary
+// vectors of varying non-zero counts) instead of Delta.
 struct PlainScanOpts {
   int tstride = 1;
   const int32_t *floor_ids = nullptr;
   const int32_t *floor_scores = nullptr;
+  int l2 = 0;
 };
 hipError_t scan_plain_launch(const DbDev &db, const uint32_t *qcode, int k, int grid,
                              uint64_t *partial, hipStream_t s, const PlainScanOpts &o = PlainScanOpts());

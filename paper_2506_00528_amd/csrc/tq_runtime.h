@@ -61,6 +61,17 @@ class TimedLaunch {
   hipEvent_t a_ = nullptr, b_ = nullptr;
 };
 
+// --- device memory ------------------------------------------------------------
+// Every device allocation of the library goes through these: the bytes held
+// are counted, and an allocation that would take them past the limit set by
+// tq_set_device_limit fails with hipErrorOutOfMemory before hipMalloc runs.
+hipError_t dev_malloc_raw(void **p, size_t bytes);
+void dev_free(void *p);
+template <class T>
+hipError_t dev_malloc(T **p, size_t bytes) {
+  return dev_malloc_raw(reinterpret_cast<void **>(p), bytes);
+}
+
 // --- scratch -----------------------------------------------------------------
 struct Scratch {
   void *p = nullptr;
@@ -102,8 +113,9 @@ int default_plain_grid(const tq_db *db);
 // where sparse_preferred(), anything else the bit-plane scan.
 // With `ext` the scratch comes from that buffer (nothing is allocated and no
 // launch is timed); TQ_ERR_INVALID if one query's need does not fit in it.
+// metric: TQ_METRIC_DELTA or TQ_METRIC_L2 (not with the index-list engine).
 int search_plain(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids, int32_t *scores, int grid,
-                 int engine, hipStream_t s, const ScratchSpan *ext = nullptr);
+                 int engine, hipStream_t s, const ScratchSpan *ext = nullptr, int metric = TQ_METRIC_DELTA);
 int search_masked(tq_db *db, const float *Q, int nq, int k, int32_t *ids, float *scores, int grid, hipStream_t s);
 
 // batched.cpp

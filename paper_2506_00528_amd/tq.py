@@ -17,6 +17,8 @@ from typing import Optional, Tuple
 
 import torch  # imported first so libtq.so binds to the HIP runtime torch loaded
 
+from ._abi import declare, tq_req_stats, tq_search_opts, tq_serve_cfg  # noqa: E402
+
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtq.so")
 
 TQ_OK = 0
@@ -36,6 +38,9 @@ TQ_ENGINE_POPCOUNT = 1
 TQ_ENGINE_MATRIX = 2
 TQ_ENGINE_SPARSE = 3
 
+TQ_METRIC_DELTA = 0
+TQ_METRIC_L2 = 1
+
 TQ_MAX_D = 1024
 TQ_MAX_K = 512
 
@@ -45,7 +50,8 @@ EXPORTS = (
     "tq_db_export", "tq_db_info", "tq_db_destroy", "tq_search_knn", "tq_autotune", "tq_delta_dump", "tq_sync",
     "tq_serve_create", "tq_serve_submit", "tq_serve_poll", "tq_serve_wait", "tq_serve_cancel",
     "tq_serve_stats", "tq_serve_destroy", "tq_timing_enable", "tq_timing_read", "tq_rerank",
-    "tq_search_masked", "tq_default_x", "tq_encode_b158", "tq_search_knn_noalloc",
+    "tq_search_masked", "tq_default_x", "tq_encode_b158", "tq_search_knn_noalloc", "tq_set_device_limit",
+    "tq_device_bytes", "tq_clock_mhz",
 )
 
 
@@ -53,24 +59,6 @@ class TQError(RuntimeError):
     def __init__(self, status: int, call: str, detail: str):
         super().__init__(f"{call}: {status_str(status)}: {detail}")
         self.status = status
-
-
-class tq_search_opts(ctypes.Structure):
-    _fields_ = [("path", ctypes.c_int), ("check_queries", ctypes.c_int), ("grid", ctypes.c_int),
-                ("qtile", ctypes.c_int), ("use_graph", ctypes.c_int), ("engine", ctypes.c_int),
-                ("reserved", ctypes.c_int * 2)]
-
-
-class tq_serve_cfg(ctypes.Structure):
-    _fields_ = [("budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int), ("max_k", ctypes.c_int),
-                ("n_segments", ctypes.c_int), ("max_request_nq", ctypes.c_int),
-                ("reserved", ctypes.c_int * 4)]
-
-
-class tq_req_stats(ctypes.Structure):
-    _fields_ = [("submit_ns", ctypes.c_uint64), ("admit_ns", ctypes.c_uint64),
-                ("complete_ns", ctypes.c_uint64), ("nq", ctypes.c_int), ("k", ctypes.c_int),
-                ("ticks", ctypes.c_int), ("reserved", ctypes.c_int)]
 
 
 _lib = None
@@ -84,42 +72,7 @@ def lib(path: Optional[str] = None):
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise RuntimeError(f"HIP library {p} is not built; run python -m paper_2506_00528_amd.build first")
-    L = ctypes.CDLL(p)
-    vp, i32, i64, u64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t
-    P = ctypes.POINTER
-    sig = {
-        "tq_status_str": ([i32], ctypes.c_char_p),
-        "tq_last_error": ([], ctypes.c_char_p),
-        "tq_version": ([], i32),
-        "tq_code_words": ([i32], i32),
-        "tq_default_x": ([i32], i32),
-        "tq_encode": ([vp, i64, i32, i32, vp, vp], i32),
-        "tq_encode_b158": ([vp, i64, i32, vp, vp], i32),
-        "tq_db_create": ([vp, i64, i32, i32, vp, P(vp)], i32),
-        "tq_db_export": ([vp, vp, vp], i32),
-        "tq_db_info": ([vp, P(i64), P(i32), P(i32), P(sz)], i32),
-        "tq_db_destroy": ([vp], i32),
-        "tq_search_knn": ([vp, vp, i32, i32, vp, vp, P(tq_search_opts), vp], i32),
-        "tq_search_knn_noalloc": ([vp, vp, i32, i32, vp, vp, P(tq_search_opts), vp], i32),
-        "tq_autotune": ([vp, i32, P(i32), i32, vp], i32),
-        "tq_delta_dump": ([vp, vp, i32, vp, vp], i32),
-        "tq_rerank": ([vp, i64, i32, vp, i32, vp, i32, i32, vp, vp, vp], i32),
-        "tq_search_masked": ([vp, vp, i32, i32, vp, vp, P(tq_search_opts), vp], i32),
-        "tq_sync": ([vp], i32),
-        "tq_serve_create": ([vp, P(tq_serve_cfg), P(vp)], i32),
-        "tq_serve_submit": ([vp, vp, i32, i32, P(u64)], i32),
-        "tq_serve_poll": ([vp, u64, vp, vp, P(tq_req_stats)], i32),
-        "tq_serve_wait": ([vp, u64, i32, vp, vp, P(tq_req_stats)], i32),
-        "tq_serve_cancel": ([vp, u64], i32),
-        "tq_serve_stats": ([vp, P(u64), P(u64), P(u64), P(u64)], i32),
-        "tq_serve_destroy": ([vp], i32),
-        "tq_timing_enable": ([i32], i32),
-        "tq_timing_read": ([i32, P(ctypes.c_double), P(i64), i32], i32),
-    }
-    for name, (args, res) in sig.items():
-        f = getattr(L, name)
-        f.argtypes = args
-        f.restype = res
+    L = declare(ctypes.CDLL(p))
     if path is None:
         _lib = L
     return L
@@ -270,19 +223,23 @@ def tq_db_export(db: tq_db, codes: Optional[torch.Tensor] = None, stream=None) -
     return codes
 
 
-def _opts(path=TQ_PATH_AUTO, check_queries=False, grid=0, qtile=0, use_graph=1, engine=TQ_ENGINE_AUTO):
+def _opts(path=TQ_PATH_AUTO, check_queries=False, grid=0, qtile=0, use_graph=1, engine=TQ_ENGINE_AUTO,
+          metric=TQ_METRIC_DELTA):
     o = tq_search_opts()
     o.path, o.check_queries, o.grid, o.qtile, o.use_graph = int(path), int(bool(check_queries)), int(grid), \
         int(qtile), int(use_graph)
     o.engine = int(engine)
+    o.metric = int(metric)
     return o
 
 
 def tq_search_knn(db: tq_db, qcodes: torch.Tensor, k: int, path: int = TQ_PATH_AUTO, check_queries: bool = False,
                   grid: int = 0, qtile: int = 0, use_graph: int = 1, engine: int = TQ_ENGINE_AUTO,
                   ids: Optional[torch.Tensor] = None,
-                  scores: Optional[torch.Tensor] = None, stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
-    """Top-k (ids, scores) of every query code, nearest first (Delta desc, id asc)."""
+                  scores: Optional[torch.Tensor] = None, stream=None,
+                  metric: int = TQ_METRIC_DELTA) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Top-k (ids, scores) of every query code, nearest first (score desc, id
+    asc); the score is Delta, or 2 Delta - nnz(v) with metric=TQ_METRIC_L2."""
     if qcodes.dim() != 2 or qcodes.shape[1] != 2 * db.W:
         raise ValueError("qcodes must be nq x 2W for the database's d")
     nq = int(qcodes.shape[0])
@@ -291,7 +248,7 @@ def tq_search_knn(db: tq_db, qcodes: torch.Tensor, k: int, path: int = TQ_PATH_A
             ids = torch.empty((nq, k), dtype=torch.int32, device=db.device)
         if scores is None:
             scores = torch.empty((nq, k), dtype=torch.int32, device=db.device)
-        o = _opts(path, check_queries, grid, qtile, use_graph, engine)
+        o = _opts(path, check_queries, grid, qtile, use_graph, engine, metric)
         _check(lib().tq_search_knn(db.handle, _dev(qcodes, "qcodes", torch.int32), nq, int(k),
                                    _dev(ids, "ids", torch.int32), _dev(scores, "scores", torch.int32),
                                    ctypes.byref(o), _stream(qcodes, stream)), "tq_search_knn")
@@ -300,7 +257,7 @@ def tq_search_knn(db: tq_db, qcodes: torch.Tensor, k: int, path: int = TQ_PATH_A
 
 def tq_search_knn_noalloc(db: tq_db, qcodes: torch.Tensor, k: int, ids: torch.Tensor, scores: torch.Tensor,
                           path: int = TQ_PATH_PLAIN, grid: int = 0, engine: int = TQ_ENGINE_AUTO,
-                          check_queries: bool = False, stream=None) -> None:
+                          check_queries: bool = False, stream=None, metric: int = TQ_METRIC_DELTA) -> None:
     """tq_search_knn's plain path into caller-provided ids / scores, with the
     library's fixed scratch array (no device allocation in the call)."""
     if qcodes.dim() != 2 or qcodes.shape[1] != 2 * db.W:
@@ -309,7 +266,7 @@ def tq_search_knn_noalloc(db: tq_db, qcodes: torch.Tensor, k: int, ids: torch.Te
     if tuple(ids.shape) != (nq, k) or tuple(scores.shape) != (nq, k):
         raise ValueError("ids and scores must be nq x k")
     with torch.cuda.device(db.device):
-        o = _opts(path, check_queries, grid, 0, 1, engine)
+        o = _opts(path, check_queries, grid, 0, 1, engine, metric)
         _check(lib().tq_search_knn_noalloc(db.handle, _dev(qcodes, "qcodes", torch.int32), nq, int(k),
                                            _dev(ids, "ids", torch.int32), _dev(scores, "scores", torch.int32),
                                            ctypes.byref(o), _stream(qcodes, stream)), "tq_search_knn_noalloc")
@@ -374,6 +331,25 @@ def tq_rerank(X: torch.Tensor, Q: torch.Tensor, cand: torch.Tensor, k: int, ids:
     return ids, scores
 
 
+def tq_set_device_limit(nbytes: int) -> None:
+    """Bound on the device memory the library holds (0 = none)."""
+    _check(lib().tq_set_device_limit(int(nbytes)), "tq_set_device_limit")
+
+
+def tq_device_bytes() -> int:
+    """Device bytes the library holds now."""
+    v = ctypes.c_uint64()
+    _check(lib().tq_device_bytes(ctypes.byref(v)), "tq_device_bytes")
+    return int(v.value)
+
+
+def tq_clock_mhz(stream=None) -> float:
+    """Shader clock of the current device in MHz, measured under load."""
+    v = ctypes.c_double()
+    _check(lib().tq_clock_mhz(ctypes.byref(v), _stream(None, stream)), "tq_clock_mhz")
+    return float(v.value)
+
+
 def tq_timing_enable(on: bool = True) -> None:
     _check(lib().tq_timing_enable(int(bool(on))), "tq_timing_enable")
 
@@ -392,12 +368,13 @@ class tq_server:
     the request has finished, or None while it is pending."""
 
     def __init__(self, db: tq_db, budget_bytes: int = 0, max_slots: int = 0, max_k: int = 0, n_segments: int = 0,
-                 max_request_nq: int = 0):
+                 max_request_nq: int = 0, tick_timeout_us: int = 0):
         import numpy as np  # noqa: F401
         self.db = db
         cfg = tq_serve_cfg()
         cfg.budget_bytes, cfg.max_slots, cfg.max_k = int(budget_bytes), int(max_slots), int(max_k)
         cfg.n_segments, cfg.max_request_nq = int(n_segments), int(max_request_nq)
+        cfg.tick_timeout_us = int(tick_timeout_us)
         self._h = ctypes.c_void_p()
         self._k = {}
         with torch.cuda.device(db.device):

@@ -45,50 +45,10 @@ def test_code_words(tq):
 
 
 def test_host_validation_without_gpu(tq):
-    L = tq.lib()
-    p = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
-    assert L.tq_encode(p, -1, 8, 2, p, None) == tq.TQ_ERR_INVALID
-    assert L.tq_encode(p, 4, 0, 1, p, None) == tq.TQ_ERR_INVALID
-    assert L.tq_encode(p, 4, 8, 0, p, None) == tq.TQ_ERR_INVALID
-    assert L.tq_encode(p, 4, 8, 9, p, None) == tq.TQ_ERR_INVALID
-    assert "x=9" in tq.last_error()
-    assert L.tq_encode(None, 4, 8, 2, p, None) == tq.TQ_ERR_INVALID
-    assert L.tq_encode(None, 0, 8, 2, None, None) == tq.TQ_OK  # nothing to do
-    out = ctypes.c_void_p()
-    assert L.tq_db_create(None, 10, 8, 2, None, ctypes.byref(out)) == tq.TQ_ERR_INVALID
-    assert L.tq_db_create(p, 0, 8, 2, None, ctypes.byref(out)) == tq.TQ_ERR_INVALID
-    assert L.tq_db_create(p, 2 ** 31, 8, 2, None, ctypes.byref(out)) == tq.TQ_ERR_INVALID
-    assert L.tq_db_create(p, 10, 8, 2, None, None) == tq.TQ_ERR_INVALID
-    assert L.tq_search_knn(None, p, 1, 1, p, p, None, None) == tq.TQ_ERR_INVALID
-    assert L.tq_db_export(None, p, None) == tq.TQ_ERR_INVALID
-    assert L.tq_delta_dump(None, p, 1, p, None) == tq.TQ_ERR_INVALID
-    assert L.tq_db_destroy(None) == tq.TQ_OK
-    assert L.tq_serve_destroy(None) == tq.TQ_OK
-    assert L.tq_timing_read(7, None, None, 0) == tq.TQ_ERR_INVALID
-
-
-def test_rerank_host_validation_without_gpu(tq):
-    L = tq.lib()
-    p = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
-    assert L.tq_rerank(None, 10, 8, p, 1, p, 4, 2, p, p, None) == tq.TQ_ERR_INVALID
-    assert L.tq_rerank(p, 0, 8, p, 1, p, 4, 2, p, p, None) == tq.TQ_ERR_INVALID
-    assert L.tq_rerank(p, 10, 0, p, 1, p, 4, 2, p, p, None) == tq.TQ_ERR_INVALID
-    assert L.tq_rerank(p, 10, tq.TQ_MAX_D + 1, p, 1, p, 4, 2, p, p, None) == tq.TQ_ERR_INVALID
-    assert L.tq_rerank(p, 10, 8, p, -1, p, 4, 2, p, p, None) == tq.TQ_ERR_INVALID
-    assert L.tq_rerank(p, 10, 8, p, 1, p, 0, 1, p, p, None) == tq.TQ_ERR_INVALID
-    assert L.tq_rerank(p, 10, 8, p, 1, p, tq.TQ_MAX_RERANK + 1, 2, p, p, None) == tq.TQ_ERR_INVALID
-    assert L.tq_rerank(p, 10, 8, p, 1, p, 4, 5, p, p, None) == tq.TQ_ERR_INVALID
-    assert "k=5" in tq.last_error()
-    assert L.tq_rerank(p, 10, 8, p, 1, p, 4, 0, p, p, None) == tq.TQ_ERR_INVALID
-    assert L.tq_rerank(p, 10, 8, p, 0, p, 4, 2, p, p, None) == tq.TQ_OK  # nothing to do
-
-
-def test_masked_host_validation_without_gpu(tq):
-    L = tq.lib()
-    p = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
-    assert L.tq_search_masked(None, p, 1, 1, p, p, None, None) == tq.TQ_ERR_INVALID
-    assert L.tq_timing_read(3, None, None, 0) == tq.TQ_OK  # index-list scan family
-    assert L.tq_timing_read(4, None, None, 0) == tq.TQ_ERR_INVALID
+    """Every call with invalid arguments is rejected on the host, before any
+    GPU work (the checks are shared with the sanitizer run)."""
+    from tests import abi_host_checks
+    abi_host_checks.run(tq.lib())
 
 
 def test_default_x_against_the_oracle(tq):

@@ -152,3 +152,69 @@ def test_destroy_with_work_in_flight(tq, env):
     for (q0, nq, k) in make_requests(5, 60):
         srv.submit(env["CQ"][q0:q0 + nq], k)
     srv.destroy()
+
+
+def test_watchdog_stops_the_server(tq, env):
+    """A watchdog of 1 us: no tick can finish that fast, so the first wait
+    for a tick gives up, the server stops and its requests report
+    TQ_ERR_DEVICE with the watchdog's reason; the GPU work itself finishes
+    normally and the database serves a new server afterwards."""
+    say("serving watchdog of 1 us")
+    srv = tq.tq_server(env["db"], max_k=100, tick_timeout_us=1)
+    tickets = [srv.submit(env["CQ"][i * 5:i * 5 + 5], 10) for i in range(3)]
+    tripped = 0
+    for i, t in enumerate(tickets):
+        try:
+            res = srv.wait(t, 60000)
+        except tq.TQError as e:
+            assert e.status == tq.TQ_ERR_DEVICE and "watchdog" in str(e), str(e)
+            tripped += 1
+        else:  # a tick whose event had already fired when first checked
+            check(env, (i * 5, 5, 10), res)
+    assert tripped >= 1
+    with pytest.raises(tq.TQError) as e:
+        srv.submit(env["CQ"][:2], 10)
+    assert e.value.status == tq.TQ_ERR_STATE
+    srv.destroy()
+    say("a generous watchdog lets the same requests through")
+    srv = tq.tq_server(env["db"], max_k=100, tick_timeout_us=10_000_000)
+    for i in range(3):
+        check(env, (i * 5, 5, 10), srv.wait(srv.submit(env["CQ"][i * 5:i * 5 + 5], 10), 60000))
+    srv.destroy()
+
+
+def test_device_limit_gives_nomem(tq, env):
+    """tq_set_device_limit: creating a database or a server that would take
+    the library's device memory past the limit fails with TQ_ERR_NOMEM and
+    holds nothing more; lifting the limit makes the same calls succeed."""
+    o = oracle.default()
+    rng = np.random.default_rng(5)
+    d, x = 256, 64
+    V = o.encode(rng.standard_normal((5000, d)).astype(np.float32), x)
+    codes = torch.from_numpy(o.pack(V).view(np.int32).copy()).cuda()
+    held = tq.tq_device_bytes()
+    try:
+        say("device limit: database that does not fit")
+        tq.tq_set_device_limit(held + 4096)
+        with pytest.raises(tq.TQError) as e:
+            tq.tq_db_create(codes, d, x)
+        assert e.value.status == tq.TQ_ERR_NOMEM
+        assert tq.tq_device_bytes() == held
+        say("device limit: server that does not fit")
+        with pytest.raises(tq.TQError) as e:
+            tq.tq_server(env["db"], max_k=100, max_slots=4096)
+        assert e.value.status == tq.TQ_ERR_NOMEM
+        assert tq.tq_device_bytes() == held
+    finally:
+        tq.tq_set_device_limit(0)
+    say("device limit lifted")
+    db = tq.tq_db_create(codes, d, x)
+    assert tq.tq_device_bytes() > held
+    ids, sc = tq.tq_search_knn(db, codes[:3], 5, path=tq.TQ_PATH_PLAIN)
+    torch.cuda.synchronize()
+    ei, es = o.knn(V[:3], V, 5)
+    assert np.array_equal(ids.cpu().numpy(), ei) and np.array_equal(sc.cpu().numpy(), es)
+    db.destroy()
+    srv = tq.tq_server(env["db"], max_k=100)
+    check(env, (0, 4, 100), srv.wait(srv.submit(env["CQ"][:4], 100), 60000))
+    srv.destroy()
