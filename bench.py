@@ -153,6 +153,37 @@ def run_batching(tq, torch, db, queries, x, n, W, plain_qps, args, log):
                       if db_bytes / (HBM_PEAK_GBPS * 1e9) >= 2.0 * batches[i][0] * n * d_pad / (fp4_peak * 1e12))
     floor_p = [max(db_bytes / (HBM_PEAK_GBPS * 1e9), batches[i][0] * n * ops_per_pair / (valu_peak * 1e12)) * 1e3
                for i in range(nb)]
+    # One 1 024-query k = 10 batch on the popcount engine (16-query tiles):
+    # the launch whose vector-instruction count rocprofv3 measured
+    # (profiles/popcount_counters.json, valid while the kernel sources hash
+    # the same).  Rates: the algorithmic count at 5 lane-ops per plane word
+    # (and, xor, and, two popcount-accumulates), the same at 6 per word, and
+    # the instructions the kernel actually issues (SQ_INSTS_VALU x 64 lanes).
+    pc = None
+    q1 = queries[:1024]
+    tq.tq_encode(q1, x, qc)
+    ids1, sc1 = outs[10]
+    tq.tq_search_knn(db, qc, 10, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_POPCOUNT, qtile=16, ids=ids1, scores=sc1)
+    tq.tq_timing_read(1, reset=True)
+    tq.tq_timing_enable(True)
+    for _ in range(2):
+        tq.tq_search_knn(db, qc, 10, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_POPCOUNT, qtile=16, ids=ids1,
+                         scores=sc1)
+    torch.cuda.synchronize()
+    tq.tq_timing_enable(False)
+    p_ms, p_l = tq.tq_timing_read(1, reset=True)
+    p_s = p_ms / max(1, p_l) * 1e-3
+    pairs1 = 1024 * n
+    pc = {"kernel": "scan_batched_kernel<NC, 1, 16>", "queries": 1024, "k": 10, "avg_launch_ms": round(p_s * 1e3, 4),
+          "algorithmic_5_per_word_tops": round(pairs1 * ops_per_pair / p_s / 1e12, 2),
+          "algorithmic_6_per_word_tops": round(pairs1 * 6 * 4 * ((W + 3) // 4) / p_s / 1e12, 2),
+          "peak_tops": round(valu_peak, 2)}
+    cf = os.path.join(ROOT, "profiles", "popcount_counters.json")
+    crec = json.load(open(cf)).get("scan_batched/large/k10/qt16") if os.path.exists(cf) else None
+    if crec and crec.get("source_sha") == source_sha("batched_kernels.hip", "tq_device.h") and W == 32:
+        issued = crec["valu_lane_ops_per_pair"] * pairs1 / p_s / 1e12
+        pc.update({"issued_valu_lane_ops_per_pair": crec["valu_lane_ops_per_pair"], "issued_tops": round(issued, 2),
+                   "issued_frac": round(issued / valu_peak, 4), "counters": "profiles/popcount_counters.json"})
     # consistency: a few batches against the plain path
     ok = True
     for i in (0, 7, 123):
@@ -179,7 +210,8 @@ def run_batching(tq, torch, db, queries, x, n, W, plain_qps, args, log):
                                   "ops_per_pair": ops_per_pair, "batches": nb, "launches": launches_p,
                                   "avg_launch_ms": round(kms_p / max(1, launches_p), 4),
                                   "bound_ms": round(sum(floor_p), 3), "measured_ms": round(kms_p, 3),
-                                  "frac_of_bound": round(sum(floor_p) / kms_p, 4)}}
+                                  "frac_of_bound": round(sum(floor_p) / kms_p, 4)},
+            "popcount_1024": pc}
 
 
 def run_mid_sweep(tq, torch, args, log):
