@@ -88,24 +88,31 @@ def run_batching(tq, torch, db, queries, x, n, W, plain_qps, args, log):
                 torch.empty((1024, k), dtype=torch.int32, device=dev)) for k in (1, 10, 100)}
     offs = np.cumsum([0] + [b for b, _ in batches]) % max(1, nq_pool - 1024)
 
-    def one(i):
+    def one(i, engine=tq.TQ_ENGINE_AUTO):
         b, k = batches[i]
         q0 = int(offs[i])
         tq.tq_encode(queries[q0:q0 + b], x, qc[:b])
         ids, sc = outs[k]
-        tq.tq_search_knn(db, qc[:b], k, path=tq.TQ_PATH_BATCHED, ids=ids[:b], scores=sc[:b])
+        tq.tq_search_knn(db, qc[:b], k, path=tq.TQ_PATH_BATCHED, ids=ids[:b], scores=sc[:b], engine=engine)
 
-    for i in range(3):  # warm-up: builds the graphs of these buckets
-        one(i)
-    for b in sorted({1 << j for j in range(11)}):  # every bucket's graph once, untimed
-        tq.tq_search_knn(db, qc[:b], 10, path=tq.TQ_PATH_BATCHED, ids=outs[10][0][:b], scores=outs[10][1][:b])
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for i in range(len(batches)):
-        one(i)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t
+    def stream(engine):
+        # untimed: every (batch-size bucket, k) graph of this engine once
+        for b in sorted({1 << j for j in range(11)}):
+            for k in (1, 10, 100):
+                tq.tq_search_knn(db, qc[:b], k, path=tq.TQ_PATH_BATCHED, ids=outs[k][0][:b],
+                                 scores=outs[k][1][:b], engine=engine)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for i in range(len(batches)):
+            one(i, engine)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    dt = stream(tq.TQ_ENGINE_AUTO)
     total_q = sum(b for b, _ in batches)
+    # the same stream on the popcount engine alone (the AND / popcount form of
+    # the paper's b2sp), for comparison with the default engine choice
+    dt_pop = stream(tq.TQ_ENGINE_POPCOUNT)
     # rooflines on the first 50 batches (direct launches, HIP events around each scan):
     # the matrix engine on the batches the tuned path gives it (k <= 128 from 16
     # queries), against the fp4 MFMA peak, and the popcount engine on all 50,
@@ -193,11 +200,14 @@ def run_batching(tq, torch, db, queries, x, n, W, plain_qps, args, log):
         a = tq.tq_search_knn(db, qc[:b], k, path=tq.TQ_PATH_BATCHED)
         p = tq.tq_search_knn(db, qc[:b], k, path=tq.TQ_PATH_PLAIN)
         ok &= bool(torch.equal(a[0], p[0]) and torch.equal(a[1], p[1]))
-    log(f"batching: {len(batches)} batches, {total_q} queries in {dt:.2f}s (tuning {tune_s:.1f}s)")
+    log(f"batching: {len(batches)} batches, {total_q} queries in {dt:.2f}s (tuning {tune_s:.1f}s); "
+        f"popcount engine alone {dt_pop:.2f}s")
     return {"workload": f"batching: {len(batches)} seeded batches, sizes U{{1..1024}}, k in {{1,10,100}}, "
                         f"on the N={n} d={W * 32} x={x} database",
             "queries": total_q, "seconds": round(dt, 3), "qps": round(total_q / dt, 1),
             "vs_plain": round(total_q / dt / plain_qps, 2), "autotune_s": round(tune_s, 1),
+            "popcount_engine": {"seconds": round(dt_pop, 3), "qps": round(total_q / dt_pop, 1),
+                                "vs_plain": round(total_q / dt_pop / plain_qps, 2)},
             "same_results_as_plain": ok,
             "roofline": {"kernel": "scan_mfma_group_kernel (k <= 16) + scan_mfma_kernel", "bound": "mfma", "achieved": round(tflops, 1),
                          "peak": fp4_peak, "unit": "TFLOP/s", "frac": round(tflops / fp4_peak, 4),
@@ -341,11 +351,10 @@ def run_serving(tq, torch, args, log):
            "recall_at_10": round(recall, 4), "rates": []}
     srv = tq.tq_server(db, max_k=100, max_slots=8192, max_request_nq=256, budget_bytes=1 << 30,
                        n_segments=args.serve_segments)
-    for frac in wl["rates"]:
-        rate = frac * cap_req
-        reqs = datagen.request_stream(args.serve_requests, rate, wl["mean_size"], wl["max_size"], wl["ks"])
-        offs = [(i * 37) % (4096 - 256) for i in range(len(reqs))]
-        # served: a submitter thread follows the arrival times
+
+    def served_run(server, reqs, offs):
+        """The requests submitted at their arrival times by a thread; latency
+        from the library's own time stamps."""
         tickets = [None] * len(reqs)
         start = time.perf_counter() + 0.05
 
@@ -354,7 +363,7 @@ def run_serving(tq, torch, args, log):
                 delay = start + ta - time.perf_counter()
                 if delay > 0:
                     time.sleep(delay)
-                tickets[i] = srv.submit(qhost[offs[i]:offs[i] + nq], k)
+                tickets[i] = server.submit(qhost[offs[i]:offs[i] + nq], k)
 
         th = threading.Thread(target=submitter)
         th.start()
@@ -362,15 +371,22 @@ def run_serving(tq, torch, args, log):
         for i in range(len(reqs)):
             while tickets[i] is None:
                 time.sleep(0.0002)
-            r = srv.wait(tickets[i], 600000)
+            r = server.wait(tickets[i], 600000)
             lat.append((r[2].complete_ns - r[2].submit_ns) / 1e6)
             nqs += reqs[i][1]
             first = r[2].submit_ns if first is None else min(first, r[2].submit_ns)
             last = max(last, r[2].complete_ns)
         th.join()
         span = (last - first) / 1e9  # library time stamps (CLOCK_MONOTONIC)
-        served = {"p50_ms": round(pct(lat, 50), 3), "p99_ms": round(pct(lat, 99), 3),
-                  "qps": round(nqs / max(span, 1e-9), 1)}
+        return {"p50_ms": round(pct(lat, 50), 3), "p99_ms": round(pct(lat, 99), 3),
+                "qps": round(nqs / max(span, 1e-9), 1)}
+
+    for frac in wl["rates"]:
+        rate = frac * cap_req
+        reqs = datagen.request_stream(args.serve_requests, rate, wl["mean_size"], wl["max_size"], wl["ks"])
+        offs = [(i * 37) % (4096 - 256) for i in range(len(reqs))]
+        served = served_run(srv, reqs, offs)
+        nqs = sum(nq for _, nq, _ in reqs)
         # plain: the same arrivals served first-come first-served, one request at a time
         plat = []
         pstart = time.perf_counter()
@@ -385,9 +401,18 @@ def run_serving(tq, torch, args, log):
         pspan = time.perf_counter() - pstart
         plain = {"p50_ms": round(pct(plat, 50), 3), "p99_ms": round(pct(plat, 99), 3),
                  "qps": round(nqs / pspan, 1)}
-        out["rates"].append({"load": frac, "req_per_s": round(rate, 1), "served": served, "plain": plain})
+        row = {"load": frac, "req_per_s": round(rate, 1), "served": served, "plain": plain}
+        if frac == wl["rates"][1]:
+            # the same arrivals on a server pinned to the popcount engine
+            psrv = tq.tq_server(db, max_k=100, max_slots=8192, max_request_nq=256, budget_bytes=1 << 30,
+                                n_segments=args.serve_segments, engine=tq.TQ_ENGINE_POPCOUNT)
+            row["served_popcount_engine"] = served_run(psrv, reqs, offs)
+            psrv.destroy()
+        out["rates"].append(row)
         log(f"serving load {frac}: served p50 {served['p50_ms']} ms p99 {served['p99_ms']} ms; "
-            f"plain p50 {plain['p50_ms']} ms p99 {plain['p99_ms']} ms")
+            f"plain p50 {plain['p50_ms']} ms p99 {plain['p99_ms']} ms"
+            + (f"; popcount engine p50 {row['served_popcount_engine']['p50_ms']} ms p99 "
+               f"{row['served_popcount_engine']['p99_ms']} ms" if "served_popcount_engine" in row else ""))
     st = srv.stats()
     srv.destroy()
     out["ticks"] = st["ticks"]

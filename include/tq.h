@@ -341,7 +341,10 @@ typedef struct tq_serve_cfg {
                             the server; its requests then report
                             TQ_ERR_DEVICE.  0 = no watchdog (the loop waits on
                             the GPU without polling) */
-  int reserved[3];
+  int engine;            /* TQ_ENGINE_AUTO (the default choice per tick),
+                            TQ_ENGINE_POPCOUNT or TQ_ENGINE_MATRIX (every tick
+                            whose k allows it); results are identical */
+  int reserved[2];
 } tq_serve_cfg;
 
 typedef struct tq_req_stats {

@@ -16,7 +16,7 @@ class tq_search_opts(ctypes.Structure):
 class tq_serve_cfg(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int), ("max_k", ctypes.c_int),
                 ("n_segments", ctypes.c_int), ("max_request_nq", ctypes.c_int), ("tick_timeout_us", ctypes.c_int),
-                ("reserved", ctypes.c_int * 3)]
+                ("engine", ctypes.c_int), ("reserved", ctypes.c_int * 2)]
 
 
 class tq_req_stats(ctypes.Structure):

@@ -203,7 +203,8 @@ hipError_t enqueue_tick(tq_server *s, TickPlan &p, TickStage &st) {
   const int nret = static_cast<int>(p.retire.size());
   const int kt = p.k;  // the tick's k: the largest k of the active requests
   const int nq_all = static_cast<int>(p.slots.size());
-  const bool matrix = default_engine(kt, nq_all) == TQ_ENGINE_MATRIX;
+  const int engine = s->cfg.engine == TQ_ENGINE_AUTO ? default_engine(kt, nq_all) : s->cfg.engine;
+  const bool matrix = engine == TQ_ENGINE_MATRIX && tqi::rows_for_k(kt) <= 2;
   const int qtile = matrix ? 64 : std::min(s->qtile, tqi::batched_max_qtile(kt));
   tqi::BatchParams b;
   const int64_t lo = p.seg * s->seg_tiles;
@@ -456,6 +457,8 @@ int tq_serve_create(const tq_db *db, const tq_serve_cfg *cfg, tq_server **out) {
   if (c.max_request_nq < 1) return fail(TQ_ERR_INVALID, "max_request_nq=%d", c.max_request_nq);
   if (c.n_segments < 0) return fail(TQ_ERR_INVALID, "n_segments=%d", c.n_segments);
   if (c.tick_timeout_us < 0) return fail(TQ_ERR_INVALID, "tick_timeout_us=%d", c.tick_timeout_us);
+  if (c.engine != TQ_ENGINE_AUTO && c.engine != TQ_ENGINE_POPCOUNT && c.engine != TQ_ENGINE_MATRIX)
+    return fail(TQ_ERR_INVALID, "engine=%d: serving takes AUTO, POPCOUNT or MATRIX", c.engine);
 
   tq_server *s = new (std::nothrow) tq_server();
   if (!s) return fail(TQ_ERR_NOMEM, "host allocation");

@@ -368,13 +368,14 @@ class tq_server:
     the request has finished, or None while it is pending."""
 
     def __init__(self, db: tq_db, budget_bytes: int = 0, max_slots: int = 0, max_k: int = 0, n_segments: int = 0,
-                 max_request_nq: int = 0, tick_timeout_us: int = 0):
+                 max_request_nq: int = 0, tick_timeout_us: int = 0, engine: int = TQ_ENGINE_AUTO):
         import numpy as np  # noqa: F401
         self.db = db
         cfg = tq_serve_cfg()
         cfg.budget_bytes, cfg.max_slots, cfg.max_k = int(budget_bytes), int(max_slots), int(max_k)
         cfg.n_segments, cfg.max_request_nq = int(n_segments), int(max_request_nq)
         cfg.tick_timeout_us = int(tick_timeout_us)
+        cfg.engine = int(engine)
         self._h = ctypes.c_void_p()
         self._k = {}
         with torch.cuda.device(db.device):

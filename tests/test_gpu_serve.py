@@ -218,3 +218,30 @@ def test_device_limit_gives_nomem(tq, env):
     srv = tq.tq_server(env["db"], max_k=100)
     check(env, (0, 4, 100), srv.wait(srv.submit(env["CQ"][:4], 100), 60000))
     srv.destroy()
+
+
+@pytest.mark.parametrize("engine", ["popcount", "matrix"])
+def test_pinned_engine_mix(tq, env, engine):
+    """A server pinned to one engine gives the oracle's rows for a mix of
+    requests submitted from four threads (k = 10 and 100, 1-32 queries)."""
+    eng = tq.TQ_ENGINE_POPCOUNT if engine == "popcount" else tq.TQ_ENGINE_MATRIX
+    reqs = make_requests(17, 40)
+    srv = tq.tq_server(env["db"], max_k=100, n_segments=2, engine=eng)
+    say(f"serve mix on the {engine} engine")
+    tickets = [None] * len(reqs)
+
+    def submitter(part):
+        for i in range(part, len(reqs), 4):
+            q0, nq, k = reqs[i]
+            tickets[i] = srv.submit(env["CQ"][q0:q0 + nq], k)
+
+    th = [threading.Thread(target=submitter, args=(p,)) for p in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    for req, t in zip(reqs, tickets):
+        check(env, req, srv.wait(t, 20000))
+    srv.destroy()
+    with pytest.raises(tq.TQError):
+        tq.tq_server(env["db"], max_k=100, engine=tq.TQ_ENGINE_SPARSE)
