@@ -141,6 +141,24 @@ hipError_t launch_mr(const DbDev &db, const float *q, int k, int grid, uint64_t 
   }
 }
 
+template <int NC, int R>
+int resident_m() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, scan_masked_kernel<NC, R>, kMaskedBlock, 0) != hipSuccess)
+    return 0;
+  return n;
+}
+
+template <int NC>
+int resident_mr(int k) {
+  switch (rows_for_k(k)) {
+    case 1: return resident_m<NC, 1>();
+    case 2: return resident_m<NC, 2>();
+    case 4: return resident_m<NC, 4>();
+    default: return resident_m<NC, 8>();
+  }
+}
+
 }  // namespace
 
 hipError_t scan_masked_launch(const DbDev &db, const float *q, int k, int grid, uint64_t *partial, hipStream_t s) {
@@ -154,6 +172,20 @@ hipError_t scan_masked_launch(const DbDev &db, const float *q, int k, int grid, 
     case 7: return launch_mr<7>(db, q, k, grid, partial, s);
     case 8: return launch_mr<8>(db, q, k, grid, partial, s);
     default: return hipErrorInvalidValue;
+  }
+}
+
+int scan_masked_resident(int nc, int k) {
+  switch (nc) {
+    case 1: return resident_mr<1>(k);
+    case 2: return resident_mr<2>(k);
+    case 3: return resident_mr<3>(k);
+    case 4: return resident_mr<4>(k);
+    case 5: return resident_mr<5>(k);
+    case 6: return resident_mr<6>(k);
+    case 7: return resident_mr<7>(k);
+    case 8: return resident_mr<8>(k);
+    default: return 0;
   }
 }
 

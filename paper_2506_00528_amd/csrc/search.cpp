@@ -121,8 +121,17 @@ int search_plain(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *ids,
 // Masked addition of float queries (one database pass per query, like the
 // plain path); the merge's int32 scores are the order-preserving key words of
 // the float scores and are turned back into floats in place.
+// The table reads need every resident slot filled to hide their latency: by
+// default one workgroup per slot on every compute unit.
+static int default_masked_grid(const tq_db *db, int k) {
+  const int64_t by_tiles = (db->dev.ntiles + 3) / 4;
+  const int per_cu = std::max(2, tqi::scan_masked_resident(db->dev.nc, k));
+  const int64_t by_cu = static_cast<int64_t>(db->num_cu > 0 ? db->num_cu : 256) * per_cu;
+  return static_cast<int>(std::max<int64_t>(1, std::min(by_tiles, by_cu)));
+}
+
 int search_masked(tq_db *db, const float *Q, int nq, int k, int32_t *ids, float *scores, int grid, hipStream_t s) {
-  const int G = grid > 0 ? grid : default_plain_grid(db);
+  const int G = grid > 0 ? grid : default_masked_grid(db, k);
   const size_t per_query = static_cast<size_t>(G) * k * sizeof(uint64_t);
   const int chunk = static_cast<int>(std::max<size_t>(1, std::min<size_t>(nq, kPartialBudget / per_query)));
   const size_t mid_keys = static_cast<size_t>(tqi::merge_mid_keys(chunk, G, k));

@@ -132,6 +132,9 @@ inline bool sparse_preferred(const DbDev &db) { return db.sparse != nullptr && 1
 // scores (order-preserving key words of the float scores) into floats.
 hipError_t scan_masked_launch(const DbDev &db, const float *q, int k, int grid, uint64_t *partial, hipStream_t s);
 hipError_t rank_to_float_launch(int32_t *scores, int64_t count, hipStream_t s);
+// Workgroups of the masked scan for (nc, k) that one compute unit holds at
+// once (registers and LDS); 0 if the runtime cannot say.
+int scan_masked_resident(int nc, int k);
 
 // rerank.hip: the k best of each query's ncand candidate rows of X (n x d
 // floats) by the double-precision scalar product with the query (nq x d).
