@@ -87,11 +87,31 @@ __global__ __launch_bounds__(kMaskedBlock) void scan_masked_kernel(const uint4 *
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
         const uint32_t z = vz[c][w], g = vg[c][w];
+        // Even nibbles in the low halves of the four bytes, odd nibbles
+        // likewise: each table offset is then one byte of these words
+        // shifted by 3, a single instruction with a byte-select operand.
+        // The empty asm keeps the compiler from folding the masks back
+        // into a shift and a mask per nibble.
+        uint32_t z0 = z & 0x0F0F0F0Fu, z1 = (z >> 4) & 0x0F0F0F0Fu;
+        uint32_t g0 = g & 0x0F0F0F0Fu, g1 = (g >> 4) & 0x0F0F0F0Fu;
+        asm volatile("" : "+v"(z0), "+v"(z1), "+v"(g0), "+v"(g1));
         const double *row = lut + (4 * c + w) * 8 * 16;
+        // all sixteen reads of the word are issued before the first add
+        double e[16];
 #pragma unroll
-        for (int nib = 0; nib < 8; ++nib) {
-          sp[nib & 1] += row[nib * 16 + ((z >> (4 * nib)) & 15)];
-          sm[nib & 1] += row[nib * 16 + ((g >> (4 * nib)) & 15)];
+        for (int b = 0; b < 4; ++b) {
+          e[4 * b + 0] = row[(2 * b) * 16 + ((z0 >> (8 * b)) & 0xFF)];
+          e[4 * b + 1] = row[(2 * b) * 16 + ((g0 >> (8 * b)) & 0xFF)];
+          e[4 * b + 2] = row[(2 * b + 1) * 16 + ((z1 >> (8 * b)) & 0xFF)];
+          e[4 * b + 3] = row[(2 * b + 1) * 16 + ((g1 >> (8 * b)) & 0xFF)];
+        }
+        // nibble order within each accumulator: even nibbles into [0], odd into [1]
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          sp[0] += e[4 * b + 0];
+          sm[0] += e[4 * b + 1];
+          sp[1] += e[4 * b + 2];
+          sm[1] += e[4 * b + 3];
         }
       }
       vz[c] = load_stream(next + c * 64 + lane);
