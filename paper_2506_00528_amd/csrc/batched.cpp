@@ -251,14 +251,18 @@ int get_entry(tq_db *db, hipStream_t s, int bucket, int k, const Shape &sh, Batc
   return TQ_OK;
 }
 
-hipError_t launch_scan(tq_db *db, BatchEntry &e, int k, const Shape &sh, hipStream_t s) {
-  if (sh.engine == TQ_ENGINE_MATRIX)
-    return tqi::scan_mfma_launch(db->dev, e.qprep, e.prm, k, sh.qtile, sh.grid, e.partial, s);
+hipError_t launch_scan(tq_db *db, BatchEntry &e, int bucket, int k, const Shape &sh, hipStream_t s) {
+  if (sh.engine == TQ_ENGINE_MATRIX) {
+    // the fewest parts (so the longest) come with the most queries the entry serves
+    tqi::BatchParams widest;
+    tqi::batch_split(widest, bucket, sh.qtile, sh.grid, 0, db->dev.ntiles);
+    return tqi::scan_mfma_launch(db->dev, e.qprep, e.prm, k, sh.qtile, sh.grid, widest.tiles_per_part, e.partial, s);
+  }
   return tqi::scan_batched_launch(db->dev, e.qprep, e.prm, k, sh.qtile, sh.grid, e.partial, s);
 }
 
 int enqueue_scan_merge(tq_db *db, BatchEntry &e, int bucket, int k, const Shape &sh, hipStream_t s) {
-  hipError_t err = launch_scan(db, e, k, sh, s);
+  hipError_t err = launch_scan(db, e, bucket, k, sh, s);
   if (err != hipSuccess) return hip_fail(err, "batched scan launch");
   err = tqi::merge_batched_launch(e.partial, e.prm, bucket, k, sh.grid + tqi::kXcds, e.mid, s);
   if (err != hipSuccess) return hip_fail(err, "batched merge launch");
@@ -321,7 +325,7 @@ int run_chunk_on(tq_db *db, BatchEntry *e, const uint32_t *qcodes, int nq, int k
     // timed runs launch directly so the events bracket the scan kernel alone
     {
       TimedLaunch t(kTimeBatched, s);
-      err = launch_scan(db, *e, k, sh, s);
+      err = launch_scan(db, *e, bucket, k, sh, s);
     }
     if (err != hipSuccess) return hip_fail(err, "batched scan launch");
     err = tqi::merge_batched_launch(e->partial, e->prm, bucket, k, sh.grid + tqi::kXcds, e->mid, s);

@@ -30,6 +30,8 @@
 // builds exact keys and inserts them, in id order, into its register top-k
 // list for that query.  A query belongs to one wave, so a wave's list is the
 // (query, part) result and no merge inside the workgroup is needed.
+#include <type_traits>
+
 #include "tq_batched.h"
 #include "tq_device.h"
 
@@ -72,6 +74,42 @@ __device__ __forceinline__ float score_of(uint64_t thr) {
 __device__ __forceinline__ float row_threshold(uint64_t own, uint64_t lb) {
   return lb > own ? static_cast<float>(key_score(lb)) - 0.5f : score_of(own);
 }
+
+// Part-relative 32-bit keys for the k > 16 scan.  Within one database part
+// of at most 2^20 vectors starting at id `base`, the key
+//   ((score + kK32Bias) << 20) | (2^20 - 1 - (id - base))
+// orders (score, id) pairs exactly like the 64-bit key (score descending, then
+// id ascending): |score| <= d <= 1024, so score + kK32Bias lies in [1, 2049]
+// (12 bits) and every real key is non-zero, like the 64-bit form.
+constexpr int32_t kK32Bias = 1025;
+constexpr uint32_t kLidMask = (1u << 20) - 1;
+
+__device__ __forceinline__ int32_t score32(uint32_t key) { return static_cast<int32_t>(key >> 20) - kK32Bias; }
+
+__device__ __forceinline__ float row_threshold(uint32_t own, uint32_t lb) {
+  return lb > own ? static_cast<float>(score32(lb)) - 0.5f : (own ? static_cast<float>(score32(own)) : -1e30f);
+}
+
+// A 64-bit key from anywhere in the database as the threshold it sets on this
+// part's 32-bit keys: local > to_local(T) exactly when the 64-bit key of the
+// same (score, id) is > T.  0 stays 0 (no bound).
+__device__ __forceinline__ uint32_t to_local(uint64_t t, int64_t base) {
+  if (!t) return 0;
+  const uint32_t hi = static_cast<uint32_t>(key_score(t) + kK32Bias) << 20;
+  const int64_t id = static_cast<int64_t>(~static_cast<uint32_t>(t));
+  if (id < base) return hi | kLidMask;       // equal scores here have larger ids
+  if (id - base > kLidMask) return hi - 1u;  // equal scores here have smaller ids
+  return hi | (kLidMask - static_cast<uint32_t>(id - base));
+}
+
+__device__ __forceinline__ uint64_t to_global(uint32_t key, int64_t base) {
+  return key ? make_key(score32(key), static_cast<uint32_t>(base + (kLidMask - (key & kLidMask)))) : 0;
+}
+
+__device__ __forceinline__ uint32_t readlane_key(uint32_t v, int l) {
+  return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), l));
+}
+__device__ __forceinline__ uint64_t readlane_key(uint64_t v, int l) { return readlane64(v, l); }
 
 // Relaxed stores at device scope: the published keys are read by workgroups
 // on other XCDs, around the non-coherent L2s (min_published_keys).
@@ -121,21 +159,24 @@ struct TileStage {
 };
 
 // Two workgroups per CU (their LDS fits) wherever the registers allow it.
-template <int NC, int R, int RB, int WV>
-__global__ __launch_bounds__(64 * WV, R * RB * WV <= 8 ? 8 / WV : 1) void scan_mfma_kernel(const uint4 *__restrict__ tiles, int64_t n,
-                                                              const uint32_t *__restrict__ qprep,
-                                                              const BatchParams *__restrict__ prm, int k,
-                                                              uint64_t *__restrict__ partial) {
+// K32: keys relative to the part's first id (every part spans at most 2^20
+// vectors), half the list registers and lane moves of the 64-bit form.
+template <int NC, int R, int RB, int WV, bool K32>
+__global__ __launch_bounds__(64 * WV, (K32 ? R : 2 * R) * RB * WV <= 16 ? 8 / WV : 1) void scan_mfma_kernel(
+    const uint4 *__restrict__ tiles, int64_t n, const uint32_t *__restrict__ qprep,
+    const BatchParams *__restrict__ prm, int k, uint64_t *__restrict__ partial) {
+  using Key = typename std::conditional<K32, uint32_t, uint64_t>::type;
+  using List = typename std::conditional<K32, WaveList32<R>, WaveList<R>>::type;
   constexpr int QW = 16 * RB;            // queries per wave
   constexpr int QT = WV * QW;            // queries per workgroup tile
   __shared__ v4i op[2][NC * 4 * 64];     // two staged tiles of fp4 operands
-  __shared__ uint64_t lbs[WV * QW];      // each query's bound from the other parts
+  __shared__ Key lbs[WV * QW];           // each query's bound from the other parts
   const int j = threadIdx.x;
   const int lane = j & 63;
   const int wave = j >> 6;
   const int col = lane & 15;  // operand row / column of this lane
   const int grp = lane >> 4;  // k-block of this lane; also its output row group
-  uint64_t *const lb = lbs + wave * QW;
+  Key *const lb = lbs + wave * QW;
   const int nq = prm->nq, nqt = prm->nqt, parts = prm->parts;
   const int64_t tpp = prm->tiles_per_part;
   const int64_t tile_lo = prm->tile_lo, tile_hi = prm->tile_hi;
@@ -160,6 +201,18 @@ __global__ __launch_bounds__(64 * WV, R * RB * WV <= 8 ? 8 / WV : 1) void scan_m
     const int nact = max(0, min(QW, nq - q0));
     const int64_t t0 = tile_lo + static_cast<int64_t>(part) * tpp;
     const int64_t t1 = min(tile_hi, t0 + tpp);
+    const int64_t base = t0 * 64;  // first id of the part
+    // (score, id) -> this form's key; this form's key -> the 64-bit key
+    auto make = [&](int32_t score, int64_t id) -> Key {
+      if constexpr (K32)
+        return (static_cast<uint32_t>(score + kK32Bias) << 20) | (kLidMask - static_cast<uint32_t>(id - base));
+      else
+        return make_key(score, static_cast<uint32_t>(id));
+    };
+    auto global = [&](Key key) -> uint64_t {
+      if constexpr (K32) return to_global(key, base);
+      else return key;
+    };
 
     // operand A: this wave's queries, re-coded once per item
     v4i a[RB][NC];
@@ -177,7 +230,7 @@ __global__ __launch_bounds__(64 * WV, R * RB * WV <= 8 ? 8 / WV : 1) void scan_m
         a[rb][s] = fp4_operand(nz, ng);
       }
     }
-    WaveList<R> list[QW];
+    List list[QW];
 #pragma unroll
     for (int qi = 0; qi < QW; ++qi) list[qi].clear();
     if (lane < QW) lb[lane] = 0;
@@ -235,19 +288,19 @@ __global__ __launch_bounds__(64 * WV, R * RB * WV <= 8 ? 8 / WV : 1) void scan_m
                 // lanes of group g carry row 16 rb + 4 g + i
                 const int qi = rb * 16 + 4 * g + i;
                 if (!(rows[rb][i] & (0xFFFFull << (16 * g))) || qi >= nact) continue;
-                const uint64_t lbq = lb[qi];
-                uint64_t own = list[qi].at(km1);
-                uint64_t thr = own > lbq ? own : lbq;
+                const Key lbq = lb[qi];
+                Key own = list[qi].at(km1);
+                Key thr = own > lbq ? own : lbq;
 #pragma unroll
                 for (int cb = 0; cb < 4; ++cb) {  // increasing ids
                   const int64_t id = t * 64 + cb * 16 + col;
                   const float v = acc[rb][cb][i];
-                  const uint64_t key = make_key(static_cast<int32_t>(v), static_cast<uint32_t>(id));
-                  uint64_t m = __ballot(grp == g && id < n && key > thr) ;
+                  const Key key = make(static_cast<int32_t>(v), id);
+                  uint64_t m = __ballot(grp == g && id < n && key > thr);
                   while (m) {
                     const int src = __builtin_ctzll(m);
                     m &= m - 1;
-                    const uint64_t c = readlane64(key, src);
+                    const Key c = readlane_key(key, src);
                     if (c > thr) {
                       list[qi].insert(c);
                       own = list[qi].at(km1);
@@ -275,8 +328,8 @@ __global__ __launch_bounds__(64 * WV, R * RB * WV <= 8 ? 8 / WV : 1) void scan_m
 #pragma unroll
       for (int qi = 0; qi < QW; ++qi) {
         if (qi < nact) {
-          const uint64_t mk = list[qi].at(mth - 1);
-          if (lane == 0 && mk) store_shared_key(bound + static_cast<int64_t>(q0 + qi) * parts + part, mk);
+          const Key mk = list[qi].at(mth - 1);
+          if (lane == 0 && mk) store_shared_key(bound + static_cast<int64_t>(q0 + qi) * parts + part, global(mk));
         }
       }
       const int rq = lane / kLanesPerQuery;
@@ -289,7 +342,10 @@ __global__ __launch_bounds__(64 * WV, R * RB * WV <= 8 ? 8 / WV : 1) void scan_m
         const uint64_t o = __shfl_xor(static_cast<unsigned long long>(mn), off);
         mn = o < mn ? o : mn;
       }
-      if (lane % kLanesPerQuery == 0) lb[rq] = mn;
+      if (lane % kLanesPerQuery == 0) {
+        if constexpr (K32) lb[rq] = to_local(mn, base);
+        else lb[rq] = mn;
+      }
       __builtin_amdgcn_wave_barrier();
     };
     if (t0 < t1) {
@@ -317,7 +373,7 @@ __global__ __launch_bounds__(64 * WV, R * RB * WV <= 8 ? 8 / WV : 1) void scan_m
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const int p = r * 64 + lane;
-          if (p < k) dst[p] = list[qi].v[r];
+          if (p < k) dst[p] = global(list[qi].v[r]);
         }
       }
     }
@@ -512,10 +568,14 @@ hipError_t launch_g(const DbDev &db, const uint32_t *qprep, const BatchParams *p
 }
 
 template <int NC, int R, int RB, int WV = kMfmaWaves>
-hipError_t launch_m3(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int grid,
+hipError_t launch_m3(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int grid, bool k32,
                      uint64_t *partial, hipStream_t s) {
-  hipLaunchKernelGGL((scan_mfma_kernel<NC, R, RB, WV>), dim3(grid), dim3(64 * WV), 0, s, db.tiles, db.n, qprep, prm,
-                     k, partial);
+  if (k32)
+    hipLaunchKernelGGL((scan_mfma_kernel<NC, R, RB, WV, true>), dim3(grid), dim3(64 * WV), 0, s, db.tiles, db.n,
+                       qprep, prm, k, partial);
+  else
+    hipLaunchKernelGGL((scan_mfma_kernel<NC, R, RB, WV, false>), dim3(grid), dim3(64 * WV), 0, s, db.tiles, db.n,
+                       qprep, prm, k, partial);
   return hipGetLastError();
 }
 
@@ -523,18 +583,19 @@ hipError_t launch_m3(const DbDev &db, const uint32_t *qprep, const BatchParams *
 
 template <int NC>
 hipError_t scan_mfma_launch_nc(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile,
-                               int grid, uint64_t *partial, hipStream_t s) {
+                               int grid, int64_t max_part_tiles, uint64_t *partial, hipStream_t s) {
+  const bool k32 = max_part_tiles * 64 <= static_cast<int64_t>(kLidMask) + 1;
   if (k <= kGroupMaxK) {
     if (qtile == 64) return launch_g<NC, 1>(db, qprep, prm, k, grid, partial, s);
     if (qtile == 128) return launch_g<NC, 1, 8>(db, qprep, prm, k, grid, partial, s);  // eight waves of 16
     return launch_g<NC, 2, 8>(db, qprep, prm, k, grid, partial, s);  // 256: eight waves of 32
   }
   const int r = rows_for_k(k);
-  if (qtile == 64) return r == 1 ? launch_m3<NC, 1, 1>(db, qprep, prm, k, grid, partial, s)
-                                 : launch_m3<NC, 2, 1>(db, qprep, prm, k, grid, partial, s);
+  if (qtile == 64) return r == 1 ? launch_m3<NC, 1, 1>(db, qprep, prm, k, grid, k32, partial, s)
+                                 : launch_m3<NC, 2, 1>(db, qprep, prm, k, grid, k32, partial, s);
   // 128-query tiles: eight waves of 16 queries share each staged tile
-  return r == 1 ? launch_m3<NC, 1, 1, 8>(db, qprep, prm, k, grid, partial, s)
-                : launch_m3<NC, 2, 1, 8>(db, qprep, prm, k, grid, partial, s);
+  return r == 1 ? launch_m3<NC, 1, 1, 8>(db, qprep, prm, k, grid, k32, partial, s)
+                : launch_m3<NC, 2, 1, 8>(db, qprep, prm, k, grid, k32, partial, s);
 }
 
 // This file is compiled once per plane width (-DTQ_NC=1..8), so that the
@@ -543,6 +604,6 @@ hipError_t scan_mfma_launch_nc(const DbDev &db, const uint32_t *qprep, const Bat
 #error "compile mfma_kernels.hip with -DTQ_NC=<1..8>"
 #endif
 template hipError_t scan_mfma_launch_nc<TQ_NC>(const DbDev &, const uint32_t *, const BatchParams *, int, int, int,
-                                               uint64_t *, hipStream_t);
+                                               int64_t, uint64_t *, hipStream_t);
 
 }  // namespace tqi

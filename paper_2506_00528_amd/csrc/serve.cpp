@@ -233,7 +233,8 @@ hipError_t enqueue_tick(tq_server *s, TickPlan &p, TickStage &st) {
   if (e != hipSuccess) return e;
   {
     TimedLaunch t(kTimeBatched, s->stream);
-    e = matrix ? tqi::scan_mfma_launch(db, s->d_qtick, s->d_prm, kt, qtile, s->grid, s->d_partial, s->stream)
+    e = matrix ? tqi::scan_mfma_launch(db, s->d_qtick, s->d_prm, kt, qtile, s->grid, b.tiles_per_part, s->d_partial,
+                                       s->stream)
                : tqi::scan_batched_launch(db, s->d_qtick, s->d_prm, kt, qtile, s->grid, s->d_partial, s->stream);
   }
   if (e != hipSuccess) return e;

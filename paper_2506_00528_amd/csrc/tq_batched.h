@@ -84,12 +84,14 @@ hipError_t scan_batched_launch(const DbDev &db, const uint32_t *qprep, const Bat
 // query tiles of 64 or 128 per workgroup, and k <= kGroupMaxK also with 256.
 constexpr int kGroupMaxK = 16;
 bool mfma_supported(int k, int qtile);
+// max_part_tiles: an upper bound on prm->tiles_per_part for this launch (the
+// k > 16 scan keys ids relative to their part where parts span <= 2^20 vectors).
 hipError_t scan_mfma_launch(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile,
-                            int grid, uint64_t *partial, hipStream_t s);
+                            int grid, int64_t max_part_tiles, uint64_t *partial, hipStream_t s);
 // one plane width (mfma_kernels.hip, compiled per NC); called by scan_mfma_launch
 template <int NC>
 hipError_t scan_mfma_launch_nc(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile,
-                               int grid, uint64_t *partial, hipStream_t s);
+                               int grid, int64_t max_part_tiles, uint64_t *partial, hipStream_t s);
 // Per-query merge of the (query, part) lists; the query count, part count and
 // output pointers come from `prm`; at most max_parts parts per query.  With
 // prm->running set, each query's running list joins the merge and receives

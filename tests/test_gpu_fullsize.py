@@ -109,8 +109,9 @@ def test_large_exact(tq, o):
     of 18 sampled queries (a running merge over the oracle's search of each
     chunk) equals the plain path's top-10 / top-100 and the batched path's
     rows at batch sizes 12 ... 600 and k = 1, 10, 100, with default and with
-    autotuned shapes; masked addition of 4 float queries equals the oracle's
-    masked top-10."""
+    autotuned shapes, and on the matrix engine with parts of more than 2^20
+    vectors; masked addition of 4 float queries equals the oracle's masked
+    top-10."""
     w = datagen.WORKLOADS["large"]
     n, d, x, k = w["n"], w["d"], w["x"], w["k"]
     dev = torch.device("cuda", 0)
@@ -180,6 +181,15 @@ def test_large_exact(tq, o):
                 ip2, sp2 = tq.tq_search_knn(db, qc2[:nq], kk, path=tq.TQ_PATH_PLAIN)
                 torch.cuda.synchronize()
                 assert torch.equal(ib, ip2) and torch.equal(sb, sp2), ("batched vs plain", nq, kk)
+    # the matrix engine with parts of more than 2^20 vectors (a grid of 8 or 16
+    # workgroups: 8 parts of 19 532 tiles), where its k > 16 scan keeps 64-bit
+    # keys instead of keys relative to the part's first id
+    for nq, kk, grid in ((16, 100, 8), (130, 50, 16)):
+        say(f"large full size: matrix engine, 8 parts of 1.25 M vectors, nq={nq} k={kk} grid={grid}")
+        ib, sb = tq.tq_search_knn(db, qc2[:nq], kk, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_MATRIX,
+                                  qtile=64, grid=grid)
+        torch.cuda.synchronize()
+        check_rows(ib, sb, [r for r in SAMPLED if r < nq], kk, f"wide parts nq={nq} k={kk}")
     # masked addition of the float queries against the oracle's masked
     # top-10 (both sum in double and round once; a query whose float scores
     # differ -- a double sum within ~1e-12 of a rounding boundary -- is
