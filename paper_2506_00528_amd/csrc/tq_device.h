@@ -188,38 +188,6 @@ struct WaveList {
   }
 };
 
-// The same list with 32-bit keys (one register per 64 positions, one lane
-// move per register and insertion).
-template <int R>
-struct WaveList32 {
-  uint32_t v[R];
-
-  __device__ __forceinline__ void clear() {
-#pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = 0;
-  }
-
-  __device__ __forceinline__ uint32_t at(int p) const {
-    uint32_t res = 0;
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-      if (r == (p >> 6)) res = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v[r]), p & 63));
-    return res;
-  }
-
-  __device__ __forceinline__ void insert(uint32_t key) {
-    uint32_t prev[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const uint32_t carry =
-          (r == 0) ? ~0u : static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v[r - 1]), 63));
-      prev[r] = __builtin_amdgcn_update_dpp(carry, v[r], kDppWaveShr1, 0xf, 0xf, false);
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = (v[r] > key) ? v[r] : ((prev[r] > key) ? key : prev[r]);
-  }
-};
-
 // Offer this lane's key (valid only where `ok`) to the wave's list; `thr` is
 // the current k-th key (uniform), updated in place, and never below `floor`
 // (keys at or below it are known to be outside the result).  Candidates are
