@@ -52,15 +52,21 @@ __host__ __device__ inline void item_coords(int item, int nqt, int *qt, int *par
   *part = (r / nqt) * kXcds + x;
 }
 
-// Fill of the derived split of a batch over tiles [lo, hi).
+// Fill of the derived split of a batch over tiles [lo, hi).  The grid is
+// persistent (one workgroup per resident slot), so the items are sized to
+// take one round: the most parts (a multiple of 8) with nqt x parts <= grid.
+// A count rounded up instead would leave a few items for a second round and
+// nearly double the launch (3 query tiles on 512 workgroups: 528 items).
+// Only where the query tiles alone exceed grid / 8 do the items take several
+// rounds, at 8 parts.
 __host__ __device__ inline void batch_split(BatchParams &b, int nq, int qtile, int grid, int64_t lo, int64_t hi) {
   b.nq = nq;
   b.nqt = (nq + qtile - 1) / qtile;
   const int64_t ntiles = hi - lo;
-  int64_t parts = b.nqt > 0 ? (grid + b.nqt - 1) / b.nqt : 1;
+  int64_t parts = b.nqt > 0 ? grid / b.nqt : 1;
   if (parts > ntiles) parts = ntiles;
   if (parts < 1) parts = 1;
-  parts = (parts + kXcds - 1) / kXcds * kXcds;
+  parts = parts >= kXcds ? parts / kXcds * kXcds : kXcds;
   b.parts = static_cast<int>(parts);
   b.l2 = 0;
   b.running_stride = 0;
