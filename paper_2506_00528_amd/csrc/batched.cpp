@@ -232,17 +232,16 @@ int get_entry(tq_db *db, hipStream_t s, int bucket, int k, const Shape &sh, Batc
   }
   BatchEntry e;
   const size_t qbytes = static_cast<size_t>(bucket) * 8 * db->dev.nc * sizeof(uint32_t);
-  // (query, part) lists: nq * parts <= qtile * grid + nq, plus up to 7 parts
-  // per query from rounding the part count to a multiple of the XCD count
-  const size_t lists = static_cast<size_t>(sh.qtile) * sh.grid + static_cast<size_t>(tqi::kXcds + 1) * bucket;
+  // (query, part) lists of any split of up to `bucket` queries
+  const size_t lists = tqi::batch_max_lists(sh.qtile, sh.grid, bucket);
   hipError_t err = dev_malloc(&e.qprep, qbytes);
   if (err == hipSuccess) err = dev_malloc(&e.prm, sizeof(tqi::BatchParams));
   if (err == hipSuccess) err = dev_malloc(&e.partial, lists * k * sizeof(uint64_t));
   if (err == hipSuccess) err = dev_malloc(&e.bound, lists * tqi::kBoundSlotsPerPart * sizeof(uint64_t));
   if (err == hipSuccess) err = hipEventCreateWithFlags(&e.done, hipEventDisableTiming);
   if (err == hipSuccess)
-    err = dev_malloc(&e.mid, static_cast<size_t>(tqi::merge_batched_mid_keys(bucket, sh.grid + tqi::kXcds, k)) *
-                                sizeof(uint64_t));
+    err = dev_malloc(&e.mid, static_cast<size_t>(tqi::merge_batched_mid_keys(bucket, tqi::batch_max_parts(sh.grid),
+                                                                              k)) * sizeof(uint64_t));
   if (err != hipSuccess) {
     free_entry(e);
     return hip_fail(err, "device allocation (batched buffers)");
@@ -253,10 +252,15 @@ int get_entry(tq_db *db, hipStream_t s, int bucket, int k, const Shape &sh, Batc
 
 hipError_t launch_scan(tq_db *db, BatchEntry &e, int bucket, int k, const Shape &sh, hipStream_t s) {
   if (sh.engine == TQ_ENGINE_MATRIX) {
-    // the fewest parts (so the longest) come with the most queries the entry serves
-    tqi::BatchParams widest;
-    tqi::batch_split(widest, bucket, sh.qtile, sh.grid, 0, db->dev.ntiles);
-    return tqi::scan_mfma_launch(db->dev, e.qprep, e.prm, k, sh.qtile, sh.grid, widest.tiles_per_part, e.partial, s);
+    // the longest part of any split the entry's graph may replay (up to
+    // `bucket` queries): one split per query-tile count
+    int64_t widest = 0;
+    for (int nqt = 1; (nqt - 1) * sh.qtile < bucket; ++nqt) {
+      tqi::BatchParams b;
+      tqi::batch_split(b, std::min(nqt * sh.qtile, bucket), sh.qtile, sh.grid, 0, db->dev.ntiles);
+      widest = std::max(widest, b.tiles_per_part);
+    }
+    return tqi::scan_mfma_launch(db->dev, e.qprep, e.prm, k, sh.qtile, sh.grid, widest, e.partial, s);
   }
   return tqi::scan_batched_launch(db->dev, e.qprep, e.prm, k, sh.qtile, sh.grid, e.partial, s);
 }
@@ -264,7 +268,7 @@ hipError_t launch_scan(tq_db *db, BatchEntry &e, int bucket, int k, const Shape 
 int enqueue_scan_merge(tq_db *db, BatchEntry &e, int bucket, int k, const Shape &sh, hipStream_t s) {
   hipError_t err = launch_scan(db, e, bucket, k, sh, s);
   if (err != hipSuccess) return hip_fail(err, "batched scan launch");
-  err = tqi::merge_batched_launch(e.partial, e.prm, bucket, k, sh.grid + tqi::kXcds, e.mid, s);
+  err = tqi::merge_batched_launch(e.partial, e.prm, bucket, k, tqi::batch_max_parts(sh.grid), e.mid, s);
   if (err != hipSuccess) return hip_fail(err, "batched merge launch");
   return TQ_OK;
 }
@@ -328,7 +332,7 @@ int run_chunk_on(tq_db *db, BatchEntry *e, const uint32_t *qcodes, int nq, int k
       err = launch_scan(db, *e, bucket, k, sh, s);
     }
     if (err != hipSuccess) return hip_fail(err, "batched scan launch");
-    err = tqi::merge_batched_launch(e->partial, e->prm, bucket, k, sh.grid + tqi::kXcds, e->mid, s);
+    err = tqi::merge_batched_launch(e->partial, e->prm, bucket, k, tqi::batch_max_parts(sh.grid), e->mid, s);
     if (err != hipSuccess) return hip_fail(err, "batched merge launch");
     return TQ_OK;
   }

@@ -238,7 +238,8 @@ hipError_t enqueue_tick(tq_server *s, TickPlan &p, TickStage &st) {
                : tqi::scan_batched_launch(db, s->d_qtick, s->d_prm, kt, qtile, s->grid, s->d_partial, s->stream);
   }
   if (e != hipSuccess) return e;
-  e = tqi::merge_batched_launch(s->d_partial, s->d_prm, nq, kt, s->grid + tqi::kXcds, s->d_mid, s->stream);
+  e = tqi::merge_batched_launch(s->d_partial, s->d_prm, nq, kt, tqi::batch_max_parts(s->grid), s->d_mid,
+                                s->stream);
   if (e != hipSuccess) return e;
   // retiring requests: results to pinned host memory
   if (nret) {
@@ -497,13 +498,13 @@ int tq_serve_create(const tq_db *db, const tq_serve_cfg *cfg, tq_server **out) {
   dm((void **)&s->d_qtick, M * 8 * nc * sizeof(uint32_t));
   dm((void **)&s->d_running, M * s->k_run * sizeof(uint64_t));
   // query tiles of up to 64 (matrix engine) or s->qtile (popcount engine)
-  dm((void **)&s->d_partial,
-     (static_cast<size_t>(std::max(64, s->qtile)) * s->grid + (tqi::kXcds + 1) * M) * s->k_run * sizeof(uint64_t));
-  dm((void **)&s->d_bound, (static_cast<size_t>(std::max(64, s->qtile)) * s->grid + (tqi::kXcds + 1) * M) *
-                               tqi::kBoundSlotsPerPart * sizeof(uint64_t));
+  const size_t lists = tqi::batch_max_lists(std::max(64, s->qtile), s->grid, static_cast<int>(M));
+  dm((void **)&s->d_partial, lists * s->k_run * sizeof(uint64_t));
+  dm((void **)&s->d_bound, lists * tqi::kBoundSlotsPerPart * sizeof(uint64_t));
   int64_t mid_keys = 0;
   for (int k = 1; k <= s->k_run; ++k)
-    mid_keys = std::max(mid_keys, tqi::merge_batched_mid_keys(static_cast<int>(M), s->grid + tqi::kXcds, k));
+    mid_keys =
+        std::max(mid_keys, tqi::merge_batched_mid_keys(static_cast<int>(M), tqi::batch_max_parts(s->grid), k));
   dm((void **)&s->d_mid, static_cast<size_t>(mid_keys) * sizeof(uint64_t));
   dm((void **)&s->d_tick, sizeof(tqi::BatchParams) + 2 * M * sizeof(int));
   if (e == hipSuccess) {

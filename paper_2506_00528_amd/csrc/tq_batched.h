@@ -53,26 +53,49 @@ __host__ __device__ inline void item_coords(int item, int nqt, int *qt, int *par
 }
 
 // Fill of the derived split of a batch over tiles [lo, hi).  The grid is
-// persistent (one workgroup per resident slot), so the items are sized to
-// take one round: the most parts (a multiple of 8) with nqt x parts <= grid.
-// A count rounded up instead would leave a few items for a second round and
-// nearly double the launch (3 query tiles on 512 workgroups: 528 items).
-// Only where the query tiles alone exceed grid / 8 do the items take several
-// rounds, at 8 parts.
+// persistent: its workgroups take items (query tile, part) in rounds of
+// `grid`, and a launch lasts about rounds x (tiles per part).  The part count
+// (a multiple of 8) minimises rounds / parts over one or two rounds; two
+// rounds must promise a tenth less, since more parts also cost list fills and
+// merge work.  So nq x parts <= kMaxRounds x qtile x grid + 8 nq (the list
+// buffers' size) and parts <= kMaxRounds x grid + 8 (the merge's bound).  A count rounded up from grid / nqt instead would leave a
+// few items for a second round and nearly double the launch (3 query tiles
+// on 512 workgroups: 528 items); one round of fewer items can instead leave
+// compute units with a single workgroup (40 query tiles: 320 items), where
+// two full rounds of smaller parts finish sooner.
+constexpr int kMaxRounds = 2;
 __host__ __device__ inline void batch_split(BatchParams &b, int nq, int qtile, int grid, int64_t lo, int64_t hi) {
   b.nq = nq;
   b.nqt = (nq + qtile - 1) / qtile;
   const int64_t ntiles = hi - lo;
-  int64_t parts = b.nqt > 0 ? grid / b.nqt : 1;
-  if (parts > ntiles) parts = ntiles;
-  if (parts < 1) parts = 1;
-  parts = parts >= kXcds ? parts / kXcds * kXcds : kXcds;
+  const int64_t cap = (ntiles + kXcds - 1) / kXcds * kXcds;  // no more parts than tiles, rounded up
+  int64_t parts = kXcds;
+  if (b.nqt > 0 && grid > 0) {
+    int64_t best_rounds = 0;
+    for (int r = 1; r <= kMaxRounds; ++r) {
+      int64_t p = static_cast<int64_t>(r) * grid / (static_cast<int64_t>(kXcds) * b.nqt) * kXcds;
+      if (p > cap) p = cap;
+      if (p < kXcds) p = kXcds;
+      const int64_t rounds = (static_cast<int64_t>(b.nqt) * p + grid - 1) / grid;
+      if (r == 1 || 10 * rounds * parts < 9 * best_rounds * p) {
+        parts = p;
+        best_rounds = rounds;
+      }
+    }
+  }
   b.parts = static_cast<int>(parts);
   b.l2 = 0;
   b.running_stride = 0;
   b.tiles_per_part = (ntiles + parts - 1) / parts;
   b.tile_lo = lo;
   b.tile_hi = hi;
+}
+
+// Bounds that hold for every split of up to `nq` queries on `grid`
+// workgroups: the parts of one query, and the (query, part) lists of a call.
+inline int batch_max_parts(int grid) { return kMaxRounds * grid + kXcds; }
+inline size_t batch_max_lists(int qtile, int grid, int nq) {
+  return static_cast<size_t>(kMaxRounds) * qtile * grid + static_cast<size_t>(kXcds + 1) * nq;
 }
 
 // Largest query tile the batched scan supports for this k.
