@@ -55,9 +55,10 @@ __host__ __device__ inline void item_coords(int item, int nqt, int *qt, int *par
 // Fill of the derived split of a batch over tiles [lo, hi).  The grid is
 // persistent: its workgroups take items (query tile, part) in rounds of
 // `grid`, and a launch lasts about rounds x (tiles per part).  The part count
-// (a multiple of 8) minimises rounds / parts over one or two rounds; two
-// rounds must promise a tenth less, since more parts also cost list fills and
-// merge work.  So nq x parts <= kMaxRounds x qtile x grid + 8 nq (the list
+// (a multiple of 8) minimises rounds / parts over one or two rounds; a
+// second round is considered only where one round leaves more than a quarter
+// of the grid idle, and must then promise a tenth less, since more parts also
+// cost list fills (k keys each) and merge work.  So nq x parts <= kMaxRounds x qtile x grid + 8 nq (the list
 // buffers' size) and parts <= kMaxRounds x grid + 8 (the merge's bound).  A count rounded up from grid / nqt instead would leave a
 // few items for a second round and nearly double the launch (3 query tiles
 // on 512 workgroups: 528 items); one round of fewer items can instead leave
@@ -81,6 +82,8 @@ __host__ __device__ inline void batch_split(BatchParams &b, int nq, int qtile, i
         parts = p;
         best_rounds = rounds;
       }
+      // one round that fills three quarters of the grid is kept
+      if (r == 1 && 4 * static_cast<int64_t>(b.nqt) * p >= 3 * static_cast<int64_t>(grid)) break;
     }
   }
   b.parts = static_cast<int>(parts);
