@@ -33,12 +33,15 @@ struct Shape {
   int grid = 0;
   bool plain = false;  // the plain path was faster for this bucket
   int engine = TQ_ENGINE_POPCOUNT;
+  float ms = 0.f;      // tuned time of a full bucket (0: not timed)
 };
 
 // ---------------------------------------------------------------------------
 // tuning cache: key "nc<nc>/kc<k class>/b<bucket>/t<log2 tiles>" -> Shape
 // (the database's size class is part of the key: the best grid and the
-// plain / batched split depend on it); optional JSON file.  The k class
+// plain / batched split depend on it), and the same key + "/q<qtile>" -> the
+// best matrix-engine shape with that query tile and its time; optional JSON
+// file.  The k class
 // separates every set of k that has its own kernels and valid query tiles:
 // k <= kGroupMaxK (the matrix engine's grouped lists, 256-query tiles), then
 // one class per list depth R = rows_for_k(k) above that.
@@ -58,9 +61,12 @@ int size_class(int64_t ntiles) {
 
 int k_class(int k) { return k <= tqi::kGroupMaxK ? 0 : tqi::rows_for_k(k); }
 
-std::string tune_key(const tqi::DbDev &db, int k, int bucket) {
+std::string tune_key(const tqi::DbDev &db, int k, int bucket, int qtile = 0) {
   char b[80];
-  std::snprintf(b, sizeof b, "nc%d/kc%d/b%d/t%d", db.nc, k_class(k), bucket, size_class(db.ntiles));
+  if (qtile)
+    std::snprintf(b, sizeof b, "nc%d/kc%d/b%d/t%d/q%d", db.nc, k_class(k), bucket, size_class(db.ntiles), qtile);
+  else
+    std::snprintf(b, sizeof b, "nc%d/kc%d/b%d/t%d", db.nc, k_class(k), bucket, size_class(db.ntiles));
   return b;
 }
 
@@ -78,8 +84,12 @@ void tune_load_locked() {
     char key[64];
     Shape s;
     int plain = 0;
-    if (std::sscanf(line, " \"%63[^\"]\": {\"qtile\": %d, \"grid\": %d, \"plain\": %d, \"engine\": %d}", key,
-                    &s.qtile, &s.grid, &plain, &s.engine) == 5) {
+    const int got = std::sscanf(line,
+                                " \"%63[^\"]\": {\"qtile\": %d, \"grid\": %d, \"plain\": %d, \"engine\": %d, "
+                                "\"ms\": %f}",
+                                key, &s.qtile, &s.grid, &plain, &s.engine, &s.ms);
+    if (got >= 5) {  // files written before the time was stored have none
+      if (got == 5) s.ms = 0.f;
       s.plain = plain != 0;
       g_tune.map[key] = s;
     }
@@ -96,28 +106,28 @@ void tune_save_locked() {
   std::fprintf(fp, "{\n");
   size_t i = 0;
   for (auto &kv : g_tune.map) {
-    std::fprintf(fp, " \"%s\": {\"qtile\": %d, \"grid\": %d, \"plain\": %d, \"engine\": %d}%s\n",
+    std::fprintf(fp, " \"%s\": {\"qtile\": %d, \"grid\": %d, \"plain\": %d, \"engine\": %d, \"ms\": %.4f}%s\n",
                  kv.first.c_str(), kv.second.qtile, kv.second.grid, kv.second.plain ? 1 : 0, kv.second.engine,
-                 ++i < g_tune.map.size() ? "," : "");
+                 kv.second.ms, ++i < g_tune.map.size() ? "," : "");
   }
   std::fprintf(fp, "}\n");
   std::fclose(fp);
   std::rename(tmp.c_str(), f);
 }
 
-bool tune_lookup(const tqi::DbDev &db, int k, int bucket, Shape *out) {
+bool tune_lookup(const tqi::DbDev &db, int k, int bucket, Shape *out, int qtile = 0) {
   std::lock_guard<std::mutex> g(g_tune.mu);
   tune_load_locked();
-  auto it = g_tune.map.find(tune_key(db, k, bucket));
+  auto it = g_tune.map.find(tune_key(db, k, bucket, qtile));
   if (it == g_tune.map.end()) return false;
   *out = it->second;
   return true;
 }
 
-void tune_store(const tqi::DbDev &db, int k, int bucket, const Shape &s) {
+void tune_store(const tqi::DbDev &db, int k, int bucket, const Shape &s, int qtile = 0) {
   std::lock_guard<std::mutex> g(g_tune.mu);
   tune_load_locked();
-  g_tune.map[tune_key(db, k, bucket)] = s;
+  g_tune.map[tune_key(db, k, bucket, qtile)] = s;
   tune_save_locked();
 }
 
@@ -189,7 +199,7 @@ struct BatchEntry {
 // Entries kept per database; beyond this the least recently used one is freed
 // (after its latest use has finished), so that many distinct k, buckets or
 // streams do not hold device memory without bound.
-constexpr size_t kMaxEntries = 64;
+constexpr size_t kMaxEntries = 96;
 
 struct BatchedState {
   hipStream_t capture = nullptr;
@@ -357,11 +367,33 @@ bool shape_valid(const Shape &sh, int k) {
   return (sh.qtile == 2 || sh.qtile == 4 || sh.qtile == 8 || sh.qtile == 16) && sh.qtile <= tqi::batched_max_qtile(k);
 }
 
-Shape shape_for(tq_db *db, int k, int bucket, const tq_search_opts *opts) {
+// The tuned matrix shape whose time at a full bucket, scaled by the query
+// tiles `nq` queries fill against the tiles of the full bucket, is least:
+// a bucket's queries fill its tiles, a smaller batch may fill fewer of a
+// smaller tile (600 queries: three 256-query tiles out of four, or five
+// 128-query tiles out of eight).  `sh` when no alternative was timed.
+Shape tile_for(const tq_db *db, int k, int bucket, int nq, const Shape &sh) {
+  Shape best = sh;
+  double best_est = 1e300;
+  for (int qt : {64, 128, 256}) {
+    Shape c;
+    if (!tqi::mfma_supported(k, qt) || !tune_lookup(db->dev, k, bucket, &c, qt) || c.ms <= 0.f) continue;
+    const double est = static_cast<double>(c.ms) * ((nq + qt - 1) / qt) / ((bucket + qt - 1) / qt);
+    if (est < best_est) {
+      best_est = est;
+      best = c;
+    }
+  }
+  return best;
+}
+
+Shape shape_for(tq_db *db, int k, int bucket, int nq, const tq_search_opts *opts) {
   Shape sh;
   if (!tune_lookup(db->dev, k, bucket, &sh) || !shape_valid(sh, k)) sh = default_shape(db, k, bucket);
   int engine = opts ? opts->engine : TQ_ENGINE_AUTO;
   const int qtile = opts ? opts->qtile : 0;
+  const bool any_matrix = engine == TQ_ENGINE_AUTO || engine == TQ_ENGINE_MATRIX;
+  if (sh.engine == TQ_ENGINE_MATRIX && !sh.plain && qtile == 0 && any_matrix) sh = tile_for(db, k, bucket, nq, sh);
   if (engine == TQ_ENGINE_AUTO && qtile > 0) engine = qtile >= 64 ? TQ_ENGINE_MATRIX : TQ_ENGINE_POPCOUNT;
   // the l2 order (2 Delta - nnz(v)) is scored by the popcount engine only
   if (engine == TQ_ENGINE_AUTO && opts && opts->metric == TQ_METRIC_L2) engine = TQ_ENGINE_POPCOUNT;
@@ -415,7 +447,8 @@ int search_batched(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *id
         return fail(TQ_ERR_INVALID, "matrix engine: qtile=%d is not 64 or 128 (or 256 for k <= %d)", q,
                     tqi::kGroupMaxK);
     } else {
-      if (q != 2 && q != 4 && q != 8 && q != 16) return fail(TQ_ERR_INVALID, "qtile=%d is not 2, 4, 8, 16, 64 or 128", q);
+      if (q != 2 && q != 4 && q != 8 && q != 16)
+        return fail(TQ_ERR_INVALID, "qtile=%d is not 2, 4, 8, 16, 64 or 128", q);
       if (q > tqi::batched_max_qtile(k))
         return fail(TQ_ERR_INVALID, "qtile=%d exceeds %d for k=%d", q, tqi::batched_max_qtile(k), k);
     }
@@ -423,7 +456,7 @@ int search_batched(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *id
   const int row_words = 2 * db->dev.W;
   for (int q0 = 0; q0 < nq; q0 += kMaxBucket) {
     const int m = std::min(kMaxBucket, nq - q0);
-    const Shape sh = shape_for(db, k, bucket_of(m), opts);
+    const Shape sh = shape_for(db, k, bucket_of(m), m, opts);
     int rc = run_chunk(db, qcodes + static_cast<int64_t>(q0) * row_words, m, k, ids + static_cast<int64_t>(q0) * k,
                        scores + static_cast<int64_t>(q0) * k, sh, use_graph, s, l2);
     if (rc) return rc;
@@ -591,6 +624,7 @@ int autotune(tq_db *db, int nq_max, const int *ks, int nks, hipStream_t s, int v
       }
       Shape best;
       float best_ms = 1e30f;
+      Shape per_tile[3];  // the best matrix shape with 64-, 128- and 256-query tiles
       for (const Shape &c : cands) {
         float ms = 0.f;
         rc = time_config(db, q, b, k, ids, scores, c, s, &ms);
@@ -601,8 +635,19 @@ int autotune(tq_db *db, int nq_max, const int *ks, int nks, hipStream_t s, int v
         if (ms < best_ms) {
           best_ms = ms;
           best = c;
+          best.ms = ms;
+        }
+        if (!c.plain && c.engine == TQ_ENGINE_MATRIX) {
+          Shape &t = per_tile[c.qtile == 64 ? 0 : c.qtile == 128 ? 1 : 2];
+          if (t.ms <= 0.f || ms < t.ms) {
+            t = c;
+            t.ms = ms;
+          }
         }
       }
+      if (rc == TQ_OK)
+        for (const Shape &t : per_tile)
+          if (t.ms > 0.f) tune_store(db->dev, k, b, t, t.qtile);
       if (rc == TQ_OK) {
         if (best.plain) {  // keep a batched shape for explicit batched calls
           Shape d = default_shape(db, k, b);

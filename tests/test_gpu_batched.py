@@ -307,8 +307,10 @@ def test_popcount_cross_part_bound_adversarial(tq, o, grid):
 
 def test_autotune_cache_file(tq, o, small, tmp_path, monkeypatch):
     """tq_autotune writes its choices to TQ_TUNE_CACHE, keyed by plane width,
-    k class, batch-size bucket and the database's size class; searches that
-    use them are still exact."""
+    k class, batch-size bucket and the database's size class, and per bucket
+    the best matrix shape of each query tile with its time (the key + /q<tile>);
+    searches that use them, at sizes between the buckets too, are still
+    exact."""
     import json
     import re
     path = tmp_path / "tune.json"
@@ -316,21 +318,24 @@ def test_autotune_cache_file(tq, o, small, tmp_path, monkeypatch):
     say("autotune cache file")
     tq.tq_autotune(small["db"], 16, [10])
     data = json.loads(path.read_text())
-    assert data and all(re.fullmatch(r"nc\d+/kc\d+/b\d+/t\d+", key) for key in data), list(data)[:4]
-    assert {"qtile", "grid", "plain", "engine"} <= set(next(iter(data.values())))
-    for nq in (1, 9, 16):
+    assert data and all(re.fullmatch(r"nc\d+/kc\d+/b\d+/t\d+(/q\d+)?", key) for key in data), list(data)[:4]
+    assert all({"qtile", "grid", "plain", "engine", "ms"} <= set(v) for v in data.values())
+    per_tile = {key: v for key, v in data.items() if "/q" in key}
+    assert per_tile and all(v["engine"] == tq.TQ_ENGINE_MATRIX and v["ms"] > 0 and key.endswith(f"/q{v['qtile']}")
+                            for key, v in per_tile.items()), per_tile
+    for nq in (1, 9, 12, 16):
         ids, sc = run(tq, small["db"], small["CQ"][:nq], 10, path=tq.TQ_PATH_AUTO)
         ei, es = o.knn(small["VQ"][:nq], small["V"], 10)
         assert np.array_equal(sc, es) and np.array_equal(ids, ei), nq
 
 
 def test_many_distinct_k_evicts_entries(tq, o, small):
-    """Every distinct (bucket, k, shape) keeps buffers and a graph; beyond 64
-    the least recently used is freed after its latest use.  80 values of k in
+    """Every distinct (bucket, k, shape) keeps buffers and a graph; beyond 96
+    the least recently used is freed after its latest use.  110 values of k in
     a row, each checked, then the first ones again."""
-    say("batched: 80 distinct k values")
+    say("batched: 110 distinct k values")
     CQ, VQ = small["CQ"][:3], small["VQ"][:3]
-    for k in list(range(1, 81)) + [1, 2, 3]:
+    for k in list(range(1, 111)) + [1, 2, 3]:
         ids, sc = run(tq, small["db"], CQ, k, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_POPCOUNT)
         ei, es = o.knn(VQ, small["V"], k)
         assert np.array_equal(sc, es) and np.array_equal(ids, ei), k
