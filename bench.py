@@ -164,8 +164,11 @@ def run_batching(tq, torch, db, queries, x, n, W, plain_qps, args, log):
     # the launch whose vector-instruction count rocprofv3 measured
     # (profiles/popcount_counters.json, valid while the kernel sources hash
     # the same).  Rates: the algorithmic count at 5 lane-ops per plane word
-    # (and, xor, and, two popcount-accumulates), the same at 6 per word, and
-    # the instructions the kernel actually issues (SQ_INSTS_VALU x 64 lanes).
+    # (and, xor, and, two popcount-accumulates), the same at a 6-per-word
+    # estimate, the 4 instructions per word the kernel needs (the xor and the
+    # second and are one three-input instruction, so the first two rates can
+    # exceed the instruction peak), and the instructions the kernel actually
+    # issues (SQ_INSTS_VALU x 64 lanes).
     pc = None
     q1 = queries[:1024]
     tq.tq_encode(q1, x, qc)
@@ -184,6 +187,7 @@ def run_batching(tq, torch, db, queries, x, n, W, plain_qps, args, log):
     pc = {"kernel": "scan_batched_kernel<NC, 1, 16>", "queries": 1024, "k": 10, "avg_launch_ms": round(p_s * 1e3, 4),
           "algorithmic_5_per_word_tops": round(pairs1 * ops_per_pair / p_s / 1e12, 2),
           "algorithmic_6_per_word_tops": round(pairs1 * 6 * 4 * ((W + 3) // 4) / p_s / 1e12, 2),
+          "instructions_4_per_word_tops": round(pairs1 * 4 * 4 * ((W + 3) // 4) / p_s / 1e12, 2),
           "peak_tops": round(valu_peak, 2)}
     cf = os.path.join(ROOT, "profiles", "popcount_counters.json")
     crec = json.load(open(cf)).get("scan_batched/large/k10/qt16") if os.path.exists(cf) else None

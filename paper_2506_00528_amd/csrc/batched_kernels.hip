@@ -109,6 +109,19 @@ __global__ __launch_bounds__(256) void running_results_kernel(const uint64_t *__
   scores[at] = key ? key_score(key) : 0;
 }
 
+// delta_word with each accumulation kept as one popcount-and-add: the empty
+// asm makes the running sums opaque, so the compiler cannot regroup the adds
+// into three-input sums of separate popcounts (two popcounts and an add per
+// two words instead of two popcount-accumulates).
+__device__ __forceinline__ void delta_word_chained(DeltaAcc &a, uint32_t qnz, uint32_t qng, uint32_t vnz,
+                                                   uint32_t vng) {
+  const uint32_t both = qnz & vnz;
+  const uint32_t dis = both & (qng ^ vng);
+  a.both = __popc(both) + a.both;
+  a.dis = __popc(dis) + a.dis;
+  asm volatile("" : "+v"(a.both), "+v"(a.dis));
+}
+
 template <int NC, int R, int QT>
 __global__ __launch_bounds__(kBatchBlock) void scan_batched_kernel(const uint4 *__restrict__ tiles, int64_t n,
                                                                   int64_t ntiles,
@@ -204,13 +217,21 @@ __global__ __launch_bounds__(kBatchBlock) void scan_batched_kernel(const uint4 *
       for (int qi = 0; qi < QT; ++qi) {
         if (qi < nact) {
           const uint32_t *qw = qprep + static_cast<int64_t>(q0 + qi) * (8 * NC);
+          // the query's words first (wide scalar loads, all in flight before
+          // the chained sums), then one popcount-accumulate per count and word
+          uint32_t qn[4 * NC], qg[4 * NC];
+#pragma unroll
+          for (int w = 0; w < 4 * NC; ++w) {
+            qn[w] = qw[w];
+            qg[w] = qw[4 * NC + w];
+          }
           DeltaAcc a;
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
-            delta_word(a, qw[4 * c + 0], qw[4 * NC + 4 * c + 0], vz[c].x, vg[c].x);
-            delta_word(a, qw[4 * c + 1], qw[4 * NC + 4 * c + 1], vz[c].y, vg[c].y);
-            delta_word(a, qw[4 * c + 2], qw[4 * NC + 4 * c + 2], vz[c].z, vg[c].z);
-            delta_word(a, qw[4 * c + 3], qw[4 * NC + 4 * c + 3], vz[c].w, vg[c].w);
+            delta_word_chained(a, qn[4 * c + 0], qg[4 * c + 0], vz[c].x, vg[c].x);
+            delta_word_chained(a, qn[4 * c + 1], qg[4 * c + 1], vz[c].y, vg[c].y);
+            delta_word_chained(a, qn[4 * c + 2], qg[4 * c + 2], vz[c].z, vg[c].z);
+            delta_word_chained(a, qn[4 * c + 3], qg[4 * c + 3], vz[c].w, vg[c].w);
           }
           const uint64_t key = make_key(delta_value(a) * mul - sub, static_cast<uint32_t>(id));
           offer_keys<R>(list[qi], thr[qi], key, ok, km1, prune ? lb[qi] : 0ull);
