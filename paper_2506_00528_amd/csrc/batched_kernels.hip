@@ -122,6 +122,25 @@ __device__ __forceinline__ void delta_word_chained(DeltaAcc &a, uint32_t qnz, ui
   asm volatile("" : "+v"(a.both), "+v"(a.dis));
 }
 
+// offer_keys with the lanes that hold a vector given as a ballot taken once
+// per tile: the candidate mask is the ballot of the compare itself, with no
+// detour through a 0/1 register
+template <int R>
+__device__ __forceinline__ void offer_keys_masked(WaveList<R> &list, uint64_t &thr, uint64_t key, uint64_t okmask,
+                                                  int k_minus_1, uint64_t floor) {
+  uint64_t m = __builtin_amdgcn_ballot_w64(key > thr) & okmask;
+  while (m) {
+    const int src = __builtin_ctzll(m);
+    m &= m - 1;
+    const uint64_t c = readlane64(key, src);
+    if (c > thr) {
+      list.insert(c);
+      thr = list.at(k_minus_1);
+      if (thr < floor) thr = floor;
+    }
+  }
+}
+
 template <int NC, int R, int QT>
 __global__ __launch_bounds__(kBatchBlock) void scan_batched_kernel(const uint4 *__restrict__ tiles, int64_t n,
                                                                   int64_t ntiles,
@@ -211,7 +230,7 @@ __global__ __launch_bounds__(kBatchBlock) void scan_batched_kernel(const uint4 *
         vg[c] = load_stream(tp + (NC + c) * 64 + lane);
       }
       const int64_t id = t * 64 + lane;
-      const bool ok = id < n;
+      const uint64_t okmask = __builtin_amdgcn_ballot_w64(id < n);
       const int32_t sub = mul == 2 ? vec_nnz<NC>(vz) : 0;
 #pragma unroll
       for (int qi = 0; qi < QT; ++qi) {
@@ -234,7 +253,7 @@ __global__ __launch_bounds__(kBatchBlock) void scan_batched_kernel(const uint4 *
             delta_word_chained(a, qn[4 * c + 3], qg[4 * c + 3], vz[c].w, vg[c].w);
           }
           const uint64_t key = make_key(delta_value(a) * mul - sub, static_cast<uint32_t>(id));
-          offer_keys<R>(list[qi], thr[qi], key, ok, km1, prune ? lb[qi] : 0ull);
+          offer_keys_masked<R>(list[qi], thr[qi], key, okmask, km1, prune ? lb[qi] : 0ull);
         }
       }
       if (prune && ++done >= next) {
