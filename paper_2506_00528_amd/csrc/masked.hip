@@ -38,10 +38,16 @@ __device__ __forceinline__ int32_t float_rank(float f) {
   return static_cast<int32_t>(k - kScoreBias);
 }
 
+// With tstride > 1 the scan covers tiles 0, tstride, 2 tstride, ... (a
+// sample); with floor_ids (the sample's merged result row of this query: k
+// ids, then its k scores in floor_scores) keys below the sample's k-th key,
+// which is never above the k-th key of the whole database, are dropped.
 template <int NC, int R>
 __global__ __launch_bounds__(kMaskedBlock) void scan_masked_kernel(const uint4 *__restrict__ tiles, int64_t n,
                                                                   int64_t ntiles, int d, const float *__restrict__ q,
-                                                                  int k, uint64_t *__restrict__ partial) {
+                                                                  int k, uint64_t *__restrict__ partial, int tstride,
+                                                                  const int32_t *__restrict__ floor_ids,
+                                                                  const int32_t *__restrict__ floor_scores) {
   constexpr int kGroups = 32 * NC;  // 4 NC words per plane, 8 nibbles per word
   __shared__ double lut[kGroups * 16];
   __shared__ uint64_t lds[2][kMaskedWaves * 64 * R];
@@ -63,24 +69,29 @@ __global__ __launch_bounds__(kMaskedBlock) void scan_masked_kernel(const uint4 *
 
   WaveList<R> list;
   list.clear();
-  uint64_t thr = 0;
+  uint64_t floor = 0;  // keys below the sample's k-th key are outside the result
+  if (floor_ids && floor_ids[k - 1] >= 0)
+    floor = make_key(floor_scores[k - 1], static_cast<uint32_t>(floor_ids[k - 1])) - 1;
+  uint64_t thr = floor;
   const int km1 = k - 1;
+  const int64_t nscan = (ntiles + tstride - 1) / tstride;  // tiles of this scan: t * tstride
+  const int64_t tile_words = static_cast<int64_t>(tstride) * (2 * NC * 64);
 
   // A chunk's registers take the same chunk of the wave's next tile as soon
   // as it has been scored, so the next tile's loads overlap this tile's table
   // reads without a second set of registers (the last tile re-reads itself).
   const int64_t t_first = static_cast<int64_t>(blockIdx.x) * kMaskedWaves + wave;
   u32x4 vz[NC], vg[NC];
-  if (t_first < ntiles) {
-    const uint4 *tile = tiles + t_first * (2 * NC * 64);
+  if (t_first < nscan) {
+    const uint4 *tile = tiles + t_first * tile_words;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       vz[c] = load_stream(tile + c * 64 + lane);
       vg[c] = load_stream(tile + (NC + c) * 64 + lane);
     }
   }
-  for (int64_t t = t_first; t < ntiles; t += nwaves) {
-    const uint4 *next = tiles + (t + nwaves < ntiles ? t + nwaves : t) * (2 * NC * 64);
+  for (int64_t t = t_first; t < nscan; t += nwaves) {
+    const uint4 *next = tiles + (t + nwaves < nscan ? t + nwaves : t) * tile_words;
     double sp[2] = {0.0, 0.0}, sm[2] = {0.0, 0.0};
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -118,9 +129,9 @@ __global__ __launch_bounds__(kMaskedBlock) void scan_masked_kernel(const uint4 *
       vg[c] = load_stream(next + (NC + c) * 64 + lane);
     }
     const float score = static_cast<float>((sp[0] + sp[1]) - 2.0 * (sm[0] + sm[1]));
-    const int64_t id = t * 64 + lane;
+    const int64_t id = t * tstride * 64 + lane;
     const uint64_t key = make_key(float_rank(score), static_cast<uint32_t>(id));
-    offer_keys<R>(list, thr, key, id < n, km1);
+    offer_keys<R>(list, thr, key, id < n, km1, floor);
   }
 
   uint64_t *a = lds[0];
@@ -145,19 +156,21 @@ __global__ void rank_to_float_kernel(int32_t *__restrict__ scores, int64_t count
 }
 
 template <int NC, int R>
-hipError_t launch_m(const DbDev &db, const float *q, int k, int grid, uint64_t *partial, hipStream_t s) {
+hipError_t launch_m(const DbDev &db, const float *q, int k, int grid, uint64_t *partial, hipStream_t s,
+                    const MaskedScanOpts &o) {
   hipLaunchKernelGGL((scan_masked_kernel<NC, R>), dim3(grid), dim3(kMaskedBlock), 0, s, db.tiles, db.n, db.ntiles,
-                     db.d, q, k, partial);
+                     db.d, q, k, partial, o.tstride, o.floor_ids, o.floor_scores);
   return hipGetLastError();
 }
 
 template <int NC>
-hipError_t launch_mr(const DbDev &db, const float *q, int k, int grid, uint64_t *partial, hipStream_t s) {
+hipError_t launch_mr(const DbDev &db, const float *q, int k, int grid, uint64_t *partial, hipStream_t s,
+                     const MaskedScanOpts &o) {
   switch (rows_for_k(k)) {
-    case 1: return launch_m<NC, 1>(db, q, k, grid, partial, s);
-    case 2: return launch_m<NC, 2>(db, q, k, grid, partial, s);
-    case 4: return launch_m<NC, 4>(db, q, k, grid, partial, s);
-    default: return launch_m<NC, 8>(db, q, k, grid, partial, s);
+    case 1: return launch_m<NC, 1>(db, q, k, grid, partial, s, o);
+    case 2: return launch_m<NC, 2>(db, q, k, grid, partial, s, o);
+    case 4: return launch_m<NC, 4>(db, q, k, grid, partial, s, o);
+    default: return launch_m<NC, 8>(db, q, k, grid, partial, s, o);
   }
 }
 
@@ -181,16 +194,18 @@ int resident_mr(int k) {
 
 }  // namespace
 
-hipError_t scan_masked_launch(const DbDev &db, const float *q, int k, int grid, uint64_t *partial, hipStream_t s) {
+hipError_t scan_masked_launch(const DbDev &db, const float *q, int k, int grid, uint64_t *partial, hipStream_t s,
+                              const MaskedScanOpts &o) {
+  if (o.tstride < 1) return hipErrorInvalidValue;
   switch (db.nc) {
-    case 1: return launch_mr<1>(db, q, k, grid, partial, s);
-    case 2: return launch_mr<2>(db, q, k, grid, partial, s);
-    case 3: return launch_mr<3>(db, q, k, grid, partial, s);
-    case 4: return launch_mr<4>(db, q, k, grid, partial, s);
-    case 5: return launch_mr<5>(db, q, k, grid, partial, s);
-    case 6: return launch_mr<6>(db, q, k, grid, partial, s);
-    case 7: return launch_mr<7>(db, q, k, grid, partial, s);
-    case 8: return launch_mr<8>(db, q, k, grid, partial, s);
+    case 1: return launch_mr<1>(db, q, k, grid, partial, s, o);
+    case 2: return launch_mr<2>(db, q, k, grid, partial, s, o);
+    case 3: return launch_mr<3>(db, q, k, grid, partial, s, o);
+    case 4: return launch_mr<4>(db, q, k, grid, partial, s, o);
+    case 5: return launch_mr<5>(db, q, k, grid, partial, s, o);
+    case 6: return launch_mr<6>(db, q, k, grid, partial, s, o);
+    case 7: return launch_mr<7>(db, q, k, grid, partial, s, o);
+    case 8: return launch_mr<8>(db, q, k, grid, partial, s, o);
     default: return hipErrorInvalidValue;
   }
 }

@@ -132,21 +132,48 @@ static int default_masked_grid(const tq_db *db, int k) {
 
 int search_masked(tq_db *db, const float *Q, int nq, int k, int32_t *ids, float *scores, int grid, hipStream_t s) {
   const int G = grid > 0 ? grid : default_masked_grid(db, k);
+  // the plain path's sample floor, on the same rule (measured on N = 1e7,
+  // d = 1024 at the default grid: k = 200 0.73 -> 0.57 ms, k = 512 1.38 ->
+  // 0.66 ms per query; at k <= 100 the sample would cost more than it saves,
+  // 0.49 -> 0.52 ms at k = 10)
+  const int64_t per_wave = db->dev.ntiles * 64 / (static_cast<int64_t>(G) * 4);
+  const bool sampled = db->dev.ntiles >= kSampleMinTiles && use_sample(per_wave, k);
   const size_t per_query = static_cast<size_t>(G) * k * sizeof(uint64_t);
-  const int chunk = static_cast<int>(std::max<size_t>(1, std::min<size_t>(nq, kPartialBudget / per_query)));
+  const size_t per_query_all = per_query + (sampled ? 2 * static_cast<size_t>(k) * sizeof(int32_t) : 0);
+  const int chunk = static_cast<int>(std::max<size_t>(1, std::min<size_t>(nq, kPartialBudget / per_query_all)));
   const size_t mid_keys = static_cast<size_t>(tqi::merge_mid_keys(chunk, G, k));
   void *p = nullptr;
-  int rc = scratch_get(db->scratch, s, per_query * chunk + mid_keys * sizeof(uint64_t), &p);
+  int rc = scratch_get(db->scratch, s, per_query_all * chunk + mid_keys * sizeof(uint64_t), &p);
   if (rc) return rc;
   uint64_t *partial = static_cast<uint64_t *>(p);
   uint64_t *mid = partial + static_cast<size_t>(chunk) * G * k;
+  // sample results: chunk x k ids, then chunk x k order-preserving score words
+  int32_t *smp_ids = reinterpret_cast<int32_t *>(mid + mid_keys);
+  int32_t *smp_scores = smp_ids + static_cast<size_t>(chunk) * k;
   int32_t *iscores = reinterpret_cast<int32_t *>(scores);
   for (int q0 = 0; q0 < nq; q0 += chunk) {
     const int nc = std::min(chunk, nq - q0);
+    if (sampled) {
+      tqi::MaskedScanOpts o;
+      o.tstride = kSampleStride;
+      for (int i = 0; i < nc; ++i) {
+        TimedLaunch t(kTimeMasked, s);
+        hipError_t e = tqi::scan_masked_launch(db->dev, Q + static_cast<int64_t>(q0 + i) * db->dev.d, k, G,
+                                               partial + static_cast<size_t>(i) * G * k, s, o);
+        if (e != hipSuccess) return hip_fail(e, "masked sample scan launch");
+      }
+      hipError_t e = tqi::merge_launch(partial, nc, G, k, smp_ids, smp_scores, mid, s);
+      if (e != hipSuccess) return hip_fail(e, "masked sample merge launch");
+    }
     for (int i = 0; i < nc; ++i) {
       TimedLaunch t(kTimeMasked, s);
+      tqi::MaskedScanOpts o;
+      if (sampled) {
+        o.floor_ids = smp_ids + static_cast<size_t>(i) * k;
+        o.floor_scores = smp_scores + static_cast<size_t>(i) * k;
+      }
       hipError_t e = tqi::scan_masked_launch(db->dev, Q + static_cast<int64_t>(q0 + i) * db->dev.d, k, G,
-                                             partial + static_cast<size_t>(i) * G * k, s);
+                                             partial + static_cast<size_t>(i) * G * k, s, o);
       if (e != hipSuccess) return hip_fail(e, "masked scan launch");
     }
     hipError_t e = tqi::merge_launch(partial, nc, G, k, ids + static_cast<int64_t>(q0) * k,

@@ -130,7 +130,16 @@ inline bool sparse_preferred(const DbDev &db) { return db.sparse != nullptr && 1
 // against the database, writing `grid` sorted lists of k keys like
 // scan_plain_launch; after merge_launch, rank_to_float_launch turns the int32
 // scores (order-preserving key words of the float scores) into floats.
-hipError_t scan_masked_launch(const DbDev &db, const float *q, int k, int grid, uint64_t *partial, hipStream_t s);
+// The masked scan's options, as PlainScanOpts: a sample scan of every
+// tstride-th tile, and the floor from a sample's merged result row (k ids,
+// then k order-preserving score words) of this query.
+struct MaskedScanOpts {
+  int tstride = 1;
+  const int32_t *floor_ids = nullptr;
+  const int32_t *floor_scores = nullptr;
+};
+hipError_t scan_masked_launch(const DbDev &db, const float *q, int k, int grid, uint64_t *partial, hipStream_t s,
+                              const MaskedScanOpts &o = MaskedScanOpts());
 hipError_t rank_to_float_launch(int32_t *scores, int64_t count, hipStream_t s);
 // Workgroups of the masked scan for (nc, k) that one compute unit holds at
 // once (registers and LDS); 0 if the runtime cannot say.

@@ -156,3 +156,42 @@ def test_masked_rejects(tq, small):
         tq.tq_search_masked(small["db"], Q, 513)
     with pytest.raises(ValueError):
         tq.tq_search_masked(small["db"], torch.zeros((2, 100), dtype=torch.float32, device="cuda"), 5)
+
+
+@pytest.mark.parametrize("grid", [0, 8, 256])
+def test_masked_sample_floor_large_k(tq, o, grid):
+    """A database of >= 2 048 tiles: where a wave scans few vectors against k,
+    masked addition first scans a sample (every 32nd tile) and the full scan
+    drops keys below the sample's k-th key -- every k here at grids 0 and 256;
+    at grid 8 (6 250 vectors per wave) k = 200 and 512 take the sample and
+    k = 100 and 128 scan without one.
+    Ternary-valued queries make the scores exact integers: each planted query
+    has copies only in tiles the sample skips plus one in sampled tile 0, and
+    every code has many exact duplicates, so the sample's k-th key ties with
+    keys of lower and higher ids elsewhere; float queries of the same database
+    are checked as the other masked tests are."""
+    rng = np.random.default_rng(73 + grid)
+    n, d, x = 200_000, 256, 64
+    base = o.encode(rng.standard_normal((3000, d)).astype(np.float32), x)
+    V = base[rng.integers(0, 3000, size=n)]  # ~67 copies of every code
+    planted = o.encode(rng.standard_normal((4, d)).astype(np.float32), x)
+    for j in range(4):
+        V[j] = planted[j]  # tile 0 is sampled
+        for c in range(30):
+            t = 1 + 32 * (c + 1) + j  # tiles the sample skips
+            V[t * 64 + 5] = planted[j]
+    VQ = np.concatenate([planted, base[:4], o.encode(rng.standard_normal((4, d)).astype(np.float32), x)])
+    Qt = VQ.astype(np.float32)
+    Qf = rng.standard_normal((6, d)).astype(np.float32)
+    db = tq.tq_db_create(dev_codes(o.pack(V)), d, x)
+    for k in (100, 128, 200, 512):
+        say(f"masked sample floor n={n} k={k} grid={grid}")
+        gi, gs = run(tq, db, Qt, k, grid=grid)
+        ei, es, _ = o.masked_knn(Qt, V, k)
+        check(gi, gs, ei, es, Qt, V, exact_required=True)
+        kid, ksc = o.knn(VQ, V, k)
+        assert np.array_equal(gi, kid) and np.array_equal(gs, ksc.astype(np.float32)), k
+        gi, gs = run(tq, db, Qf, k, grid=grid)
+        ei, es, _ = o.masked_knn(Qf, V, k)
+        check(gi, gs, ei, es, Qf, V)
+    db.destroy()
