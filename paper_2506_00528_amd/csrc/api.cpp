@@ -125,19 +125,30 @@ hipEvent_t pooled_event() {
 
 bool timing_enabled() { return g_timing_on.load(std::memory_order_relaxed) != 0; }
 
+// Timing is best effort: a pair whose events could not be had or recorded
+// is not timed, and its events go back to the pool.
 TimedLaunch::TimedLaunch(int family, hipStream_t s, bool allow) : family_(family), s_(s) {
   if (!allow || !g_timing_on.load(std::memory_order_relaxed)) return;
   std::lock_guard<std::mutex> g(g_timing.mu);
-  a_ = pooled_event();
-  b_ = pooled_event();
-  if (a_ && b_) hipEventRecord(a_, s_);
+  hipEvent_t a = pooled_event(), b = pooled_event();
+  if (a && b && hipEventRecord(a, s_) == hipSuccess) {
+    a_ = a;
+    b_ = b;
+    return;
+  }
+  if (a) g_timing.pool.push_back(a);
+  if (b) g_timing.pool.push_back(b);
 }
 
 TimedLaunch::~TimedLaunch() {
   if (!a_ || !b_) return;
   std::lock_guard<std::mutex> g(g_timing.mu);
-  hipEventRecord(b_, s_);
-  g_timing.pending[family_].emplace_back(a_, b_);
+  if (hipEventRecord(b_, s_) == hipSuccess) {
+    g_timing.pending[family_].emplace_back(a_, b_);
+  } else {
+    g_timing.pool.push_back(a_);
+    g_timing.pool.push_back(b_);
+  }
 }
 
 // ---------------------------------------------------------------------------

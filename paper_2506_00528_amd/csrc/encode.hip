@@ -32,6 +32,14 @@
 #include "tq_internal.h"
 
 namespace tqi {
+
+// The compiler's lane-write intrinsic (v_writelane_b32).  Unlike inline
+// assembly it is visible to the hazard recognizer, which inserts the wait
+// states a lane write needs when a vector compare has just written its
+// operand (a ballot written to VCC and read at once).  (Declared outside the
+// anonymous namespace: it names an intrinsic, not a function of this file.)
+__device__ int amdgcn_writelane(int val, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
 namespace {
 
 constexpr int kEncodeBlock = 256;
@@ -62,11 +70,6 @@ __device__ __forceinline__ int lanes_below(uint64_t m) {
       __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32), __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u)));
 }
 
-// The compiler's lane-write intrinsic (v_writelane_b32).  Unlike inline
-// assembly it is visible to the hazard recognizer, which inserts the wait
-// states a lane write needs when a vector compare has just written its
-// operand (a ballot written to VCC and read at once).
-__device__ int amdgcn_writelane(int val, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
 
 // v with lane L replaced by the uniform value `val`
 template <int L>
