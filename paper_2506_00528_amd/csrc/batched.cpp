@@ -190,6 +190,7 @@ struct BatchEntry {
   uint64_t *partial = nullptr;
   uint64_t *mid = nullptr;  // first-stage merge results
   uint64_t *bound = nullptr;  // per (query, part) published keys (BatchParams::bound)
+  uint64_t *floor = nullptr;  // per query: the matrix scan's sample floor (k > 16)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipEvent_t done = nullptr;  // recorded after the entry's latest use
@@ -221,6 +222,7 @@ void free_entry(BatchEntry &e) {
   if (e.partial) dev_free(e.partial);
   if (e.mid) dev_free(e.mid);
   if (e.bound) dev_free(e.bound);
+  if (e.floor) dev_free(e.floor);
   e = BatchEntry{};
 }
 
@@ -248,6 +250,7 @@ int get_entry(tq_db *db, hipStream_t s, int bucket, int k, const Shape &sh, Batc
   if (err == hipSuccess) err = dev_malloc(&e.prm, sizeof(tqi::BatchParams));
   if (err == hipSuccess) err = dev_malloc(&e.partial, lists * k * sizeof(uint64_t));
   if (err == hipSuccess) err = dev_malloc(&e.bound, lists * tqi::kBoundSlotsPerPart * sizeof(uint64_t));
+  if (err == hipSuccess) err = dev_malloc(&e.floor, static_cast<size_t>(bucket) * sizeof(uint64_t));
   if (err == hipSuccess) err = hipEventCreateWithFlags(&e.done, hipEventDisableTiming);
   if (err == hipSuccess)
     err = dev_malloc(&e.mid, static_cast<size_t>(tqi::merge_batched_mid_keys(bucket, tqi::batch_max_parts(sh.grid),
@@ -260,6 +263,14 @@ int get_entry(tq_db *db, hipStream_t s, int bucket, int k, const Shape &sh, Batc
   return TQ_OK;
 }
 
+// The matrix engine's k > 16 scan starts from a sample floor (every 32nd
+// tile scored first, scan_mfma_launch) on databases of at least 2 048 tiles,
+// where the sample holds >= 64 tiles: each (query, part) list then takes only
+// the keys above the floor instead of k keys at its start and the keys that
+// outrank them later.
+constexpr int kMfmaSampleStride = 32;
+constexpr int64_t kMfmaSampleMinTiles = 2048;
+
 hipError_t launch_scan(tq_db *db, BatchEntry &e, int bucket, int k, const Shape &sh, hipStream_t s) {
   if (sh.engine == TQ_ENGINE_MATRIX) {
     // the longest part of any split the entry's graph may replay (up to
@@ -270,7 +281,13 @@ hipError_t launch_scan(tq_db *db, BatchEntry &e, int bucket, int k, const Shape 
       tqi::batch_split(b, std::min(nqt * sh.qtile, bucket), sh.qtile, sh.grid, 0, db->dev.ntiles);
       widest = std::max(widest, b.tiles_per_part);
     }
-    return tqi::scan_mfma_launch(db->dev, e.qprep, e.prm, k, sh.qtile, sh.grid, widest, e.partial, s);
+    tqi::MfmaSample smp;
+    if (k > tqi::kGroupMaxK && db->dev.ntiles >= kMfmaSampleMinTiles) {
+      smp.stride = kMfmaSampleStride;
+      smp.bucket = bucket;
+      smp.floor = e.floor;
+    }
+    return tqi::scan_mfma_launch(db->dev, e.qprep, e.prm, k, sh.qtile, sh.grid, widest, e.partial, s, smp);
   }
   return tqi::scan_batched_launch(db->dev, e.qprep, e.prm, k, sh.qtile, sh.grid, e.partial, s);
 }

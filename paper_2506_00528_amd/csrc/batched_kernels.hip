@@ -385,17 +385,18 @@ bool mfma_supported(int k, int qtile) {
 }
 
 hipError_t scan_mfma_launch(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile,
-                            int grid, int64_t max_part_tiles, uint64_t *partial, hipStream_t s) {
+                            int grid, int64_t max_part_tiles, uint64_t *partial, hipStream_t s,
+                            const MfmaSample &sample) {
   if (!mfma_supported(k, qtile)) return hipErrorInvalidValue;
   switch (db.nc) {
-    case 1: return scan_mfma_launch_nc<1>(db, qprep, prm, k, qtile, grid, max_part_tiles, partial, s);
-    case 2: return scan_mfma_launch_nc<2>(db, qprep, prm, k, qtile, grid, max_part_tiles, partial, s);
-    case 3: return scan_mfma_launch_nc<3>(db, qprep, prm, k, qtile, grid, max_part_tiles, partial, s);
-    case 4: return scan_mfma_launch_nc<4>(db, qprep, prm, k, qtile, grid, max_part_tiles, partial, s);
-    case 5: return scan_mfma_launch_nc<5>(db, qprep, prm, k, qtile, grid, max_part_tiles, partial, s);
-    case 6: return scan_mfma_launch_nc<6>(db, qprep, prm, k, qtile, grid, max_part_tiles, partial, s);
-    case 7: return scan_mfma_launch_nc<7>(db, qprep, prm, k, qtile, grid, max_part_tiles, partial, s);
-    case 8: return scan_mfma_launch_nc<8>(db, qprep, prm, k, qtile, grid, max_part_tiles, partial, s);
+    case 1: return scan_mfma_launch_nc<1>(db, qprep, prm, k, qtile, grid, max_part_tiles, partial, s, sample);
+    case 2: return scan_mfma_launch_nc<2>(db, qprep, prm, k, qtile, grid, max_part_tiles, partial, s, sample);
+    case 3: return scan_mfma_launch_nc<3>(db, qprep, prm, k, qtile, grid, max_part_tiles, partial, s, sample);
+    case 4: return scan_mfma_launch_nc<4>(db, qprep, prm, k, qtile, grid, max_part_tiles, partial, s, sample);
+    case 5: return scan_mfma_launch_nc<5>(db, qprep, prm, k, qtile, grid, max_part_tiles, partial, s, sample);
+    case 6: return scan_mfma_launch_nc<6>(db, qprep, prm, k, qtile, grid, max_part_tiles, partial, s, sample);
+    case 7: return scan_mfma_launch_nc<7>(db, qprep, prm, k, qtile, grid, max_part_tiles, partial, s, sample);
+    case 8: return scan_mfma_launch_nc<8>(db, qprep, prm, k, qtile, grid, max_part_tiles, partial, s, sample);
     default: return hipErrorInvalidValue;
   }
 }

@@ -71,8 +71,12 @@ __device__ __forceinline__ float score_of(uint64_t thr) {
 // `lb` published by the other parts.  Keys of this part arrive in increasing
 // id order, so beating `own` takes a larger score; `lb` may come from a part
 // of higher ids, where an equal score with a lower id is a larger key.
+// A bound with the largest id field of its score (the sample floor's form)
+// cannot be beaten by an equal score, so there the prefilter admits larger
+// scores only.
 __device__ __forceinline__ float row_threshold(uint64_t own, uint64_t lb) {
-  return lb > own ? static_cast<float>(key_score(lb)) - 0.5f : score_of(own);
+  if (lb <= own) return score_of(own);
+  return static_cast<float>(key_score(lb)) - (static_cast<uint32_t>(lb) == 0xFFFFFFFFu ? 0.f : 0.5f);
 }
 
 // The wave list of tq_device.h with 32-bit keys (one register per 64
@@ -119,7 +123,8 @@ constexpr uint32_t kLidMask = (1u << 20) - 1;
 __device__ __forceinline__ int32_t score32(uint32_t key) { return static_cast<int32_t>(key >> 20) - kK32Bias; }
 
 __device__ __forceinline__ float row_threshold(uint32_t own, uint32_t lb) {
-  return lb > own ? static_cast<float>(score32(lb)) - 0.5f : (own ? static_cast<float>(score32(own)) : -1e30f);
+  if (lb <= own) return own ? static_cast<float>(score32(own)) : -1e30f;
+  return static_cast<float>(score32(lb)) - ((lb & kLidMask) == kLidMask ? 0.f : 0.5f);
 }
 
 // A 64-bit key from anywhere in the database as the threshold it sets on this
@@ -196,7 +201,7 @@ struct TileStage {
 template <int NC, int R, int RB, int WV, bool K32>
 __global__ __launch_bounds__(64 * WV, (K32 ? R : 2 * R) * RB * WV <= 16 ? 8 / WV : 1) void scan_mfma_kernel(
     const uint4 *__restrict__ tiles, int64_t n, const uint32_t *__restrict__ qprep,
-    const BatchParams *__restrict__ prm, int k, uint64_t *__restrict__ partial) {
+    const BatchParams *__restrict__ prm, int k, uint64_t *__restrict__ partial, const uint64_t *__restrict__ floor) {
   using Key = typename std::conditional<K32, uint32_t, uint64_t>::type;
   using List = typename std::conditional<K32, WaveList32<R>, WaveList<R>>::type;
   constexpr int QW = 16 * RB;            // queries per wave
@@ -221,10 +226,15 @@ __global__ __launch_bounds__(64 * WV, (K32 ? R : 2 * R) * RB * WV <= 16 ? 8 / WV
   // only grows, so any value it has published is such a T for that part, and
   // the smallest published value over the P parts (0 while one has not
   // published) is a bound for the query.
-  // (64-query tiles only: the 128-query form has no registers to spare)
+  // Behind a sample floor the exchange pays only with few parts (at most k):
+  // there the bound from m = ceil(k / P) keys per part outranks the floor,
+  // while with many parts each exchange reads many slots for a bound near
+  // the floor (on the large workload, 16 queries at k = 100 on 512 parts:
+  // 0.80 ms with the exchange, 0.70 ms without; 1 024 queries on 32 parts:
+  // 8.7 ms with it, 10.1 ms without).
   constexpr bool kPrune = RB == 1;
   constexpr int kLanesPerQuery = 64 / QW;  // lanes that read one query's bounds
-  const bool prune = kPrune && prm->bound != nullptr;
+  const bool prune = kPrune && prm->bound != nullptr && (floor == nullptr || prm->parts <= k);
 
   for (int item = blockIdx.x; item < items; item += gridDim.x) {
     int qt, part;
@@ -265,7 +275,14 @@ __global__ __launch_bounds__(64 * WV, (K32 ? R : 2 * R) * RB * WV <= 16 ? 8 / WV
     List list[QW];
 #pragma unroll
     for (int qi = 0; qi < QW; ++qi) list[qi].clear();
-    if (lane < QW) lb[lane] = 0;
+    // the sample floor (a key no final key of the query is below) starts
+    // each query's bound
+    auto floor_of = [&](int qi) -> uint64_t { return floor && qi < nact ? floor[q0 + qi] : 0; };
+    auto local = [&](uint64_t t) -> Key {
+      if constexpr (K32) return to_local(t, base);
+      else return t;
+    };
+    if (lane < QW) lb[lane] = local(floor_of(lane));
     // tv[rb][i]: k-th score of this lane's output row 16 rb + 4 grp + i;
     // rows past the real queries never pass
     float tv[RB][4];
@@ -375,8 +392,8 @@ __global__ __launch_bounds__(64 * WV, (K32 ? R : 2 * R) * RB * WV <= 16 ? 8 / WV
         mn = o < mn ? o : mn;
       }
       if (lane % kLanesPerQuery == 0) {
-        if constexpr (K32) lb[rq] = to_local(mn, base);
-        else lb[rq] = mn;
+        const uint64_t f = floor_of(rq);
+        lb[rq] = local(mn > f ? mn : f);
       }
       __builtin_amdgcn_wave_barrier();
     };
@@ -445,11 +462,16 @@ __device__ __forceinline__ uint64_t group_entry(uint64_t v, int gbase, int p) {
   return __shfl(static_cast<unsigned long long>(v), gbase + p);
 }
 
-template <int NC, int RB, int WV>
+// SAMPLE: the sample pass of the k > 16 scan -- tiles tile_lo + i tstride
+// only, i = 0, 1, ..., split over this grid like a database of that many tiles
+// (sample_split); its own instantiation, so that the full scan keeps its
+// registers.
+template <int NC, int RB, int WV, bool SAMPLE>
 __global__ __launch_bounds__(64 * WV, RB * WV <= 8 ? 8 / WV : 1) void scan_mfma_group_kernel(const uint4 *__restrict__ tiles, int64_t n,
                                                                     const uint32_t *__restrict__ qprep,
                                                                     const BatchParams *__restrict__ prm, int k,
-                                                                    uint64_t *__restrict__ partial) {
+                                                                    uint64_t *__restrict__ partial, int stride) {
+  const int tstride = SAMPLE ? stride : 1;
   constexpr int QW = 16 * RB;
   constexpr int QT = WV * QW;
   __shared__ v4i op[2][NC * 4 * 64];
@@ -459,9 +481,17 @@ __global__ __launch_bounds__(64 * WV, RB * WV <= 8 ? 8 / WV : 1) void scan_mfma_
   const int col = lane & 15;
   const int grp = lane >> 4;
   const int gbase = lane & ~15;
-  const int nq = prm->nq, nqt = prm->nqt, parts = prm->parts;
-  const int64_t tpp = prm->tiles_per_part;
-  const int64_t tile_lo = prm->tile_lo, tile_hi = prm->tile_hi;
+  BatchParams sp;
+  const BatchParams *split = prm;
+  int64_t abase = 0;  // database tile of index t: abase + t * tstride
+  if (SAMPLE) {
+    sample_split(sp, *prm, QT, static_cast<int>(gridDim.x), tstride);
+    split = &sp;
+    abase = prm->tile_lo;
+  }
+  const int nq = split->nq, nqt = split->nqt, parts = split->parts;
+  const int64_t tpp = split->tiles_per_part;
+  const int64_t tile_lo = split->tile_lo, tile_hi = split->tile_hi;
   const int items = nqt * parts;
   const int km1 = k - 1;
 
@@ -502,7 +532,7 @@ __global__ __launch_bounds__(64 * WV, RB * WV <= 8 ? 8 / WV : 1) void scan_mfma_
 
     TileStage<NC, WV> sa, sb;
     auto step = [&](int64_t t, const v4i *cur, v4i *nxt, TileStage<NC, WV> &fill, const TileStage<NC, WV> &ready) {
-      fill.load(tiles, min(t + 2, t1 - 1), j);
+      fill.load(tiles, abase + min(t + 2, t1 - 1) * tstride, j);
       if (nact > 0) {
         v4f acc[RB][4];
 #pragma unroll
@@ -546,7 +576,7 @@ __global__ __launch_bounds__(64 * WV, RB * WV <= 8 ? 8 / WV : 1) void scan_mfma_
               uint64_t thr = group_entry(L.v, gbase, km1);
 #pragma unroll
               for (int cb = 0; cb < 4; ++cb) {
-                const int64_t id = t * 64 + cb * 16 + col;
+                const int64_t id = (abase + t * tstride) * 64 + cb * 16 + col;
                 const uint64_t key = make_key(static_cast<int32_t>(acc[rb][cb][i]), static_cast<uint32_t>(id));
                 uint64_t m = __ballot(id < n && key > thr);
                 while (m) {
@@ -569,8 +599,8 @@ __global__ __launch_bounds__(64 * WV, RB * WV <= 8 ? 8 / WV : 1) void scan_mfma_
       __syncthreads();
     };
     if (t0 < t1) {
-      sa.load(tiles, t0, j);
-      sb.load(tiles, min(t0 + 1, t1 - 1), j);
+      sa.load(tiles, abase + t0 * tstride, j);
+      sb.load(tiles, abase + min(t0 + 1, t1 - 1) * tstride, j);
       sa.store(op[0], j);
       __syncthreads();
       for (int64_t t = t0; t < t1; t += 2) {
@@ -591,23 +621,103 @@ __global__ __launch_bounds__(64 * WV, RB * WV <= 8 ? 8 / WV : 1) void scan_mfma_
   }
 }
 
+// ---------------------------------------------------------------------------
+// Sample floor for k > 16
+// ---------------------------------------------------------------------------
+//
+// The sample pass keeps the top 16 keys of every (query, part) of every
+// 32nd tile.  Those keys are database keys, so if at least k of them score
+// >= s, the query's k-th key overall scores >= s and no key scoring below s
+// can be in its result.  One workgroup per query counts the sample keys per
+// score and takes the largest such s; the floor is the largest key of score
+// s - 1 (the id field of id 0), so exactly the keys scoring >= s pass it.
+constexpr int kFloorBlock = 256;
+constexpr int kScoreSpan = 1024;                            // |Delta| <= d <= 1024
+constexpr int kBinsPerThread = (2 * kScoreSpan + 1 + kFloorBlock - 1) / kFloorBlock;  // 9
+constexpr int kBins = kBinsPerThread * kFloorBlock;         // score s -> bin s + kScoreSpan
+
+__global__ __launch_bounds__(kFloorBlock) void sample_floor_kernel(const uint64_t *__restrict__ sp,
+                                                                   const BatchParams *__restrict__ prm, int qtile,
+                                                                   int grid, int tstride, int lk, int k,
+                                                                   uint64_t *__restrict__ floor) {
+  __shared__ int hist[kBins];
+  __shared__ int chunk[kFloorBlock];
+  BatchParams b;
+  sample_split(b, *prm, qtile, grid, tstride);
+  const int q = blockIdx.x;
+  if (q >= b.nq) return;
+  const int j = threadIdx.x;
+  for (int i = j; i < kBins; i += kFloorBlock) hist[i] = 0;
+  __syncthreads();
+  const int64_t cnt = static_cast<int64_t>(b.parts) * lk;
+  const uint64_t *src = sp + static_cast<int64_t>(q) * cnt;
+  for (int64_t i = j; i < cnt; i += kFloorBlock) {
+    const uint64_t key = src[i];
+    if (key) atomicAdd(&hist[min(max(key_score(key), -kScoreSpan), kScoreSpan) + kScoreSpan], 1);
+  }
+  __syncthreads();
+  int c = 0;
+#pragma unroll
+  for (int i = 0; i < kBinsPerThread; ++i) c += hist[j * kBinsPerThread + i];
+  chunk[j] = c;
+  __syncthreads();
+  if (j >= 64) return;
+  // lane l holds chunks 255 - 4l .. 252 - 4l (highest scores first)
+  int c4[4], sum = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    c4[i] = chunk[kFloorBlock - 1 - 4 * j - i];
+    sum += c4[i];
+  }
+  int incl = sum;  // keys in the chunks of lanes 0..l
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int o = __shfl_up(incl, off);
+    if (j >= off) incl += o;
+  }
+  const uint64_t reach = __ballot(incl >= k);
+  if (!reach) {
+    if (j == 0) floor[q] = 0;  // fewer than k sample keys: no floor
+    return;
+  }
+  if (j != __builtin_ctzll(reach)) return;
+  int above = incl - sum;  // keys scoring above this lane's chunks
+  for (int i = 0; i < 4; ++i) {
+    const int ch = kFloorBlock - 1 - 4 * j - i;
+    if (above + c4[i] >= k) {
+      for (int bin = ch * kBinsPerThread + kBinsPerThread - 1;; --bin) {
+        above += hist[bin];
+        if (above >= k) {
+          floor[q] = make_key(bin - kScoreSpan - 1, 0);
+          return;
+        }
+      }
+    }
+    above += c4[i];
+  }
+}
+
 template <int NC, int RB, int WV = kMfmaWaves>
 hipError_t launch_g(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int grid,
-                    uint64_t *partial, hipStream_t s) {
-  hipLaunchKernelGGL((scan_mfma_group_kernel<NC, RB, WV>), dim3(grid), dim3(64 * WV), 0, s, db.tiles, db.n, qprep,
-                     prm, k, partial);
+                    uint64_t *partial, hipStream_t s, int tstride = 1) {
+  if (tstride > 1)
+    hipLaunchKernelGGL((scan_mfma_group_kernel<NC, RB, WV, true>), dim3(grid), dim3(64 * WV), 0, s, db.tiles, db.n,
+                       qprep, prm, k, partial, tstride);
+  else
+    hipLaunchKernelGGL((scan_mfma_group_kernel<NC, RB, WV, false>), dim3(grid), dim3(64 * WV), 0, s, db.tiles, db.n,
+                       qprep, prm, k, partial, 1);
   return hipGetLastError();
 }
 
 template <int NC, int R, int RB, int WV = kMfmaWaves>
 hipError_t launch_m3(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int grid, bool k32,
-                     uint64_t *partial, hipStream_t s) {
+                     uint64_t *partial, const uint64_t *floor, hipStream_t s) {
   if (k32)
     hipLaunchKernelGGL((scan_mfma_kernel<NC, R, RB, WV, true>), dim3(grid), dim3(64 * WV), 0, s, db.tiles, db.n,
-                       qprep, prm, k, partial);
+                       qprep, prm, k, partial, floor);
   else
     hipLaunchKernelGGL((scan_mfma_kernel<NC, R, RB, WV, false>), dim3(grid), dim3(64 * WV), 0, s, db.tiles, db.n,
-                       qprep, prm, k, partial);
+                       qprep, prm, k, partial, floor);
   return hipGetLastError();
 }
 
@@ -615,19 +725,32 @@ hipError_t launch_m3(const DbDev &db, const uint32_t *qprep, const BatchParams *
 
 template <int NC>
 hipError_t scan_mfma_launch_nc(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile,
-                               int grid, int64_t max_part_tiles, uint64_t *partial, hipStream_t s) {
+                               int grid, int64_t max_part_tiles, uint64_t *partial, hipStream_t s,
+                               const MfmaSample &sample) {
   const bool k32 = max_part_tiles * 64 <= static_cast<int64_t>(kLidMask) + 1;
   if (k <= kGroupMaxK) {
     if (qtile == 64) return launch_g<NC, 1>(db, qprep, prm, k, grid, partial, s);
     if (qtile == 128) return launch_g<NC, 1, 8>(db, qprep, prm, k, grid, partial, s);  // eight waves of 16
     return launch_g<NC, 2, 8>(db, qprep, prm, k, grid, partial, s);  // 256: eight waves of 32
   }
+  const uint64_t *floor = nullptr;
+  if (sample.stride > 1) {
+    if (!sample.floor || sample.bucket < 1) return hipErrorInvalidValue;
+    hipError_t e = qtile == 64 ? launch_g<NC, 1>(db, qprep, prm, kGroupMaxK, grid, partial, s, sample.stride)
+                               : launch_g<NC, 1, 8>(db, qprep, prm, kGroupMaxK, grid, partial, s, sample.stride);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sample_floor_kernel, dim3(sample.bucket), dim3(kFloorBlock), 0, s,
+                       static_cast<const uint64_t *>(partial), prm, qtile, grid, sample.stride, kGroupMaxK, k,
+                       sample.floor);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    floor = sample.floor;
+  }
   const int r = rows_for_k(k);
-  if (qtile == 64) return r == 1 ? launch_m3<NC, 1, 1>(db, qprep, prm, k, grid, k32, partial, s)
-                                 : launch_m3<NC, 2, 1>(db, qprep, prm, k, grid, k32, partial, s);
+  if (qtile == 64) return r == 1 ? launch_m3<NC, 1, 1>(db, qprep, prm, k, grid, k32, partial, floor, s)
+                                 : launch_m3<NC, 2, 1>(db, qprep, prm, k, grid, k32, partial, floor, s);
   // 128-query tiles: eight waves of 16 queries share each staged tile
-  return r == 1 ? launch_m3<NC, 1, 1, 8>(db, qprep, prm, k, grid, k32, partial, s)
-                : launch_m3<NC, 2, 1, 8>(db, qprep, prm, k, grid, k32, partial, s);
+  return r == 1 ? launch_m3<NC, 1, 1, 8>(db, qprep, prm, k, grid, k32, partial, floor, s)
+                : launch_m3<NC, 2, 1, 8>(db, qprep, prm, k, grid, k32, partial, floor, s);
 }
 
 // This file is compiled once per plane width (-DTQ_NC=1..8), so that the
@@ -636,6 +759,6 @@ hipError_t scan_mfma_launch_nc(const DbDev &db, const uint32_t *qprep, const Bat
 #error "compile mfma_kernels.hip with -DTQ_NC=<1..8>"
 #endif
 template hipError_t scan_mfma_launch_nc<TQ_NC>(const DbDev &, const uint32_t *, const BatchParams *, int, int, int,
-                                               int64_t, uint64_t *, hipStream_t);
+                                               int64_t, uint64_t *, hipStream_t, const MfmaSample &);
 
 }  // namespace tqi

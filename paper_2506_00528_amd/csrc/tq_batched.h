@@ -94,6 +94,20 @@ __host__ __device__ inline void batch_split(BatchParams &b, int nq, int qtile, i
   b.tile_hi = hi;
 }
 
+// The split of a sample pass over every `tstride`-th tile of the call's range
+// [prm.tile_lo, prm.tile_hi): sample tile i is database tile
+// prm.tile_lo + i tstride, and the sample is split like a database of
+// ceil(range / tstride) tiles.  (Its lists only feed a floor, never a result.)
+__host__ __device__ inline void sample_split(BatchParams &b, const BatchParams &prm, int qtile, int grid,
+                                             int tstride) {
+  batch_split(b, prm.nq, qtile, grid, 0, (prm.tile_hi - prm.tile_lo + tstride - 1) / tstride);
+  b.slots = nullptr;
+  b.running = nullptr;
+  b.ids = nullptr;
+  b.scores = nullptr;
+  b.bound = nullptr;
+}
+
 // Bounds that hold for every split of up to `nq` queries on `grid`
 // workgroups: the parts of one query, and the (query, part) lists of a call.
 inline int batch_max_parts(int grid) { return kMaxRounds * grid + kXcds; }
@@ -118,12 +132,25 @@ constexpr int kGroupMaxK = 16;
 bool mfma_supported(int k, int qtile);
 // max_part_tiles: an upper bound on prm->tiles_per_part for this launch (the
 // k > 16 scan keys ids relative to their part where parts span <= 2^20 vectors).
+// Sample floor (k > 16 only; sample.stride == 0: none): a first pass scores
+// every stride-th tile with 16-key lists, a per-query histogram of those keys
+// gives the largest score s that at least k of them reach (no key of the
+// final top-k scores below s), and the full scan drops keys scoring below s.
+// sample.floor holds one key per query of the bucket; the sample's lists
+// reuse `partial` (16 < k keys per list).
+struct MfmaSample {
+  int stride = 0;
+  int bucket = 0;
+  uint64_t *floor = nullptr;
+};
 hipError_t scan_mfma_launch(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile,
-                            int grid, int64_t max_part_tiles, uint64_t *partial, hipStream_t s);
+                            int grid, int64_t max_part_tiles, uint64_t *partial, hipStream_t s,
+                            const MfmaSample &sample = MfmaSample());
 // one plane width (mfma_kernels.hip, compiled per NC); called by scan_mfma_launch
 template <int NC>
 hipError_t scan_mfma_launch_nc(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile,
-                               int grid, int64_t max_part_tiles, uint64_t *partial, hipStream_t s);
+                               int grid, int64_t max_part_tiles, uint64_t *partial, hipStream_t s,
+                               const MfmaSample &sample);
 // Per-query merge of the (query, part) lists; the query count, part count and
 // output pointers come from `prm`; at most max_parts parts per query.  With
 // prm->running set, each query's running list joins the merge and receives
