@@ -182,9 +182,9 @@ typedef struct tq_search_opts {
                         scan kernel (tuning / benchmarking) */
   int qtile;         /* 0 = auto; batched path: queries per workgroup tile:
                         2, 4, 8 or 16 on the popcount engine (at most 8 for
-                        k > 128, 4 for k > 256), 64 or 128 on the matrix
-                        engine, and also 256 there for k <= 16.  A tile of 64
-                        or more with engine AUTO selects the matrix engine. */
+                        k > 128, 4 for k > 256), 64, 128 or 256 on the
+                        matrix engine.  A tile of 64 or more with engine AUTO
+                        selects the matrix engine. */
   int use_graph;     /* batched path: 1 = replay a captured hipGraph for the
                         batch-size bucket (default when the struct is NULL),
                         0 = launch the kernels directly */

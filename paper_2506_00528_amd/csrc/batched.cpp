@@ -156,7 +156,7 @@ int mfma_resident_per_cu(int k, int qtile) {
 
 int default_matrix_qtile(int k, int bucket) {
   if (k <= tqi::kGroupMaxK) return bucket >= 512 ? 256 : bucket >= 128 ? 128 : 64;
-  return bucket >= 256 ? 128 : 64;
+  return bucket >= 512 ? 256 : bucket >= 256 ? 128 : 64;
 }
 
 Shape default_shape(const tq_db *db, int k, int bucket) {
@@ -168,7 +168,7 @@ Shape default_shape(const tq_db *db, int k, int bucket) {
   if (s.engine == TQ_ENGINE_MATRIX) {
     // (N = 1e7, d = 1024, k = 10: 1 024 queries 5.2 / 5.3 / 7.4 ms on 256 /
     // 128 / 64-query tiles, 256 queries 1.8 / 1.6 / 2.2 ms; k = 100, 1 024
-    // queries: 9.6 ms vs 10.5 ms on 128 / 64)
+    // queries: 6.8 / 8.8 ms on 256 / 128, 512 queries 3.6 / 4.8 ms)
     s.qtile = default_matrix_qtile(k, bucket);
     s.grid = cu * mfma_resident_per_cu(k, s.qtile);
   } else {
@@ -263,12 +263,14 @@ int get_entry(tq_db *db, hipStream_t s, int bucket, int k, const Shape &sh, Batc
   return TQ_OK;
 }
 
-// The matrix engine's k > 16 scan starts from a sample floor (every 32nd
+// The matrix engine's k > 16 scan starts from a sample floor (every 16th
 // tile scored first, scan_mfma_launch) on databases of at least 2 048 tiles,
-// where the sample holds >= 64 tiles: each (query, part) list then takes only
-// the keys above the floor instead of k keys at its start and the keys that
-// outrank them later.
-constexpr int kMfmaSampleStride = 32;
+// where the sample holds >= 128 tiles: each (query, part) list then takes
+// only the keys above the floor instead of k keys at its start and the keys
+// that outrank them later.  (N = 1e7, d = 1024, 1 024 queries at k = 100 on
+// 256-query tiles: 7.5 / 6.8 / 6.6 ms with every 32nd / 16th / 8th tile; 128-
+// query tiles, which also exchange bounds between parts: 8.7 / 8.8 / 9.1 ms.)
+constexpr int kMfmaSampleStride = 16;
 constexpr int64_t kMfmaSampleMinTiles = 2048;
 
 hipError_t launch_scan(tq_db *db, BatchEntry &e, int bucket, int k, const Shape &sh, hipStream_t s) {
@@ -461,8 +463,7 @@ int search_batched(tq_db *db, const uint32_t *qcodes, int nq, int k, int32_t *id
   if (q > 0) {
     if (matrix) {
       if (!tqi::mfma_supported(k, q))
-        return fail(TQ_ERR_INVALID, "matrix engine: qtile=%d is not 64 or 128 (or 256 for k <= %d)", q,
-                    tqi::kGroupMaxK);
+        return fail(TQ_ERR_INVALID, "matrix engine: qtile=%d is not 64, 128 or 256", q);
     } else {
       if (q != 2 && q != 4 && q != 8 && q != 16)
         return fail(TQ_ERR_INVALID, "qtile=%d is not 2, 4, 8, 16, 64 or 128", q);

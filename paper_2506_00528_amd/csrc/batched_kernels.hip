@@ -380,8 +380,7 @@ hipError_t scan_batched_launch(const DbDev &db, const uint32_t *qprep, const Bat
 }
 
 bool mfma_supported(int k, int qtile) {
-  if (k <= kGroupMaxK) return qtile == 64 || qtile == 128 || qtile == 256;
-  return rows_for_k(k) <= 2 && (qtile == 64 || qtile == 128);
+  return rows_for_k(k) <= 2 && (qtile == 64 || qtile == 128 || qtile == 256);
 }
 
 hipError_t scan_mfma_launch(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile,

@@ -195,11 +195,12 @@ struct TileStage {
   }
 };
 
-// Two workgroups per CU (their LDS fits) wherever the registers allow it.
+// Two workgroups per CU (their LDS fits) wherever the registers allow it;
+// RB = 2 (256-query tiles, eight waves of 32 queries) keeps two waves per SIMD.
 // K32: keys relative to the part's first id (every part spans at most 2^20
 // vectors), half the list registers and lane moves of the 64-bit form.
 template <int NC, int R, int RB, int WV, bool K32>
-__global__ __launch_bounds__(64 * WV, (K32 ? R : 2 * R) * RB * WV <= 16 ? 8 / WV : 1) void scan_mfma_kernel(
+__global__ __launch_bounds__(64 * WV, RB == 2 ? 2 : ((K32 ? R : 2 * R) * RB * WV <= 16 ? 8 / WV : 1)) void scan_mfma_kernel(
     const uint4 *__restrict__ tiles, int64_t n, const uint32_t *__restrict__ qprep,
     const BatchParams *__restrict__ prm, int k, uint64_t *__restrict__ partial, const uint64_t *__restrict__ floor) {
   using Key = typename std::conditional<K32, uint32_t, uint64_t>::type;
@@ -226,6 +227,7 @@ __global__ __launch_bounds__(64 * WV, (K32 ? R : 2 * R) * RB * WV <= 16 ? 8 / WV
   // only grows, so any value it has published is such a T for that part, and
   // the smallest published value over the P parts (0 while one has not
   // published) is a bound for the query.
+  // (RB = 2 has no registers to spare for it and relies on the floor.)
   // Behind a sample floor the exchange pays only with few parts (at most k):
   // there the bound from m = ceil(k / P) keys per part outranks the floor,
   // while with many parts each exchange reads many slots for a bound near
@@ -626,7 +628,7 @@ __global__ __launch_bounds__(64 * WV, RB * WV <= 8 ? 8 / WV : 1) void scan_mfma_
 // ---------------------------------------------------------------------------
 //
 // The sample pass keeps the top 16 keys of every (query, part) of every
-// 32nd tile.  Those keys are database keys, so if at least k of them score
+// stride-th tile.  Those keys are database keys, so if at least k of them score
 // >= s, the query's k-th key overall scores >= s and no key scoring below s
 // can be in its result.  One workgroup per query counts the sample keys per
 // score and takes the largest such s; the floor is the largest key of score
@@ -736,8 +738,11 @@ hipError_t scan_mfma_launch_nc(const DbDev &db, const uint32_t *qprep, const Bat
   const uint64_t *floor = nullptr;
   if (sample.stride > 1) {
     if (!sample.floor || sample.bucket < 1) return hipErrorInvalidValue;
+    // the sample takes the group kernel of the same query tile, so both
+    // passes and the floor kernel split the batch alike
     hipError_t e = qtile == 64 ? launch_g<NC, 1>(db, qprep, prm, kGroupMaxK, grid, partial, s, sample.stride)
-                               : launch_g<NC, 1, 8>(db, qprep, prm, kGroupMaxK, grid, partial, s, sample.stride);
+                   : qtile == 128 ? launch_g<NC, 1, 8>(db, qprep, prm, kGroupMaxK, grid, partial, s, sample.stride)
+                                  : launch_g<NC, 2, 8>(db, qprep, prm, kGroupMaxK, grid, partial, s, sample.stride);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(sample_floor_kernel, dim3(sample.bucket), dim3(kFloorBlock), 0, s,
                        static_cast<const uint64_t *>(partial), prm, qtile, grid, sample.stride, kGroupMaxK, k,
@@ -749,8 +754,12 @@ hipError_t scan_mfma_launch_nc(const DbDev &db, const uint32_t *qprep, const Bat
   if (qtile == 64) return r == 1 ? launch_m3<NC, 1, 1>(db, qprep, prm, k, grid, k32, partial, floor, s)
                                  : launch_m3<NC, 2, 1>(db, qprep, prm, k, grid, k32, partial, floor, s);
   // 128-query tiles: eight waves of 16 queries share each staged tile
-  return r == 1 ? launch_m3<NC, 1, 1, 8>(db, qprep, prm, k, grid, k32, partial, floor, s)
-                : launch_m3<NC, 2, 1, 8>(db, qprep, prm, k, grid, k32, partial, floor, s);
+  if (qtile == 128) return r == 1 ? launch_m3<NC, 1, 1, 8>(db, qprep, prm, k, grid, k32, partial, floor, s)
+                                  : launch_m3<NC, 2, 1, 8>(db, qprep, prm, k, grid, k32, partial, floor, s);
+  // 256-query tiles: eight waves of 32 queries, each B operand read feeds two
+  // products (half the LDS reads of the 128-query form per product)
+  return r == 1 ? launch_m3<NC, 1, 2, 8>(db, qprep, prm, k, grid, k32, partial, floor, s)
+                : launch_m3<NC, 2, 2, 8>(db, qprep, prm, k, grid, k32, partial, floor, s);
 }
 
 // This file is compiled once per plane width (-DTQ_NC=1..8), so that the

@@ -127,7 +127,7 @@ hipError_t batch_prep_launch(const uint32_t *qcodes, int nq, int bucket, const D
 hipError_t scan_batched_launch(const DbDev &db, const uint32_t *qprep, const BatchParams *prm, int k, int qtile,
                                int grid, uint64_t *partial, hipStream_t s);
 // The same scan on the fp4 matrix cores (mfma_kernels.hip): k <= 128 with
-// query tiles of 64 or 128 per workgroup, and k <= kGroupMaxK also with 256.
+// query tiles of 64, 128 or 256 per workgroup.
 constexpr int kGroupMaxK = 16;
 bool mfma_supported(int k, int qtile);
 // max_part_tiles: an upper bound on prm->tiles_per_part for this launch (the

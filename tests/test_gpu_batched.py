@@ -163,9 +163,8 @@ def test_autotune_large_buckets_then_other_k(tq, o, small):
 # the matrix-core engine (fp4 MFMA): same results, bit for bit
 # ---------------------------------------------------------------------------
 
-# 256-query tiles serve k <= 16 only (the others are rejected: see the argument checks)
 MATRIX_CASES = [(qtile, nq, k) for qtile in (64, 128, 256) for nq in (1, 3, 17, 100, 300)
-                for k in (1, 10, 16, 17, 64, 65, 100, 128) if qtile < 256 or k <= 16]
+                for k in (1, 10, 16, 17, 64, 65, 100, 128)]
 
 
 @pytest.mark.parametrize("qtile,nq,k", MATRIX_CASES)
@@ -217,7 +216,7 @@ def test_matrix_heavy_ties(tq, o):
     VQ = np.concatenate([base[:3], o.encode(rng.standard_normal((40, d)).astype(np.float32), x)])
     say("matrix engine heavy ties")
     db = tq.tq_db_create(dev_codes(o.pack(V)), d, x)
-    for k, qt in ((1, 64), (10, 128), (16, 256), (100, 64), (128, 128)):
+    for k, qt in ((1, 64), (10, 128), (16, 256), (100, 64), (128, 128), (100, 256)):
         ids, sc = run(tq, db, o.pack(VQ), k, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_MATRIX, qtile=qt)
         ei, es = o.knn(VQ, V, k)
         assert np.array_equal(sc, es) and np.array_equal(ids, ei), k
@@ -245,8 +244,8 @@ def test_matrix_rejects(tq, small):
         tq.tq_search_knn(small["db"], q, 200, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_MATRIX)
     with pytest.raises(tq.TQError):
         tq.tq_search_knn(small["db"], q, 10, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_MATRIX, qtile=16)
-    with pytest.raises(tq.TQError):  # 256-query tiles serve k <= 16 only
-        tq.tq_search_knn(small["db"], q, 17, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_MATRIX, qtile=256)
+    with pytest.raises(tq.TQError):  # query tiles are 64, 128 or 256
+        tq.tq_search_knn(small["db"], q, 17, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_MATRIX, qtile=512)
     with pytest.raises(tq.TQError):
         tq.tq_search_knn(small["db"], q, 10, path=tq.TQ_PATH_BATCHED, engine=7)
 

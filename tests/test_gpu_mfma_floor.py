@@ -1,6 +1,6 @@
 """The matrix engine's sample floor (k > 16 on databases of >= 2 048 tiles).
 
-Before the full scan, every 32nd tile is scored with 16-key lists per
+Before the full scan, every 16th tile is scored with 16-key lists per
 (query, part); the largest score s that at least k of those sample keys reach
 is a floor (the query's k-th key overall scores >= s), and the full scan
 drops keys scoring below s.  The result must be the exhaustive top-k of the
@@ -11,8 +11,8 @@ about 500 times at random ids, so the queries made from hubs meet hundreds of
 keys of one score -- more than k -- spread over sampled and unsampled tiles:
 the floor then sits exactly at the k-th score and every tie at it must reach
 the result by id.  The other queries are noisy database rows.  Results are
-compared with the oracle's exhaustive top-k at k = 17, 64, 100, 128, on 64-
-and 128-query tiles, at the default grid and on 8 workgroups."""
+compared with the oracle's exhaustive top-k at k = 17, 64, 100, 128, on 64-,
+128- and 256-query tiles, at the default grid and on 8 workgroups."""
 import sys
 
 import numpy as np
@@ -73,7 +73,7 @@ def test_floor_matches_oracle(tq, o, setup, k):
     ei, es = o.knn(VQ, V, k)
     # the hub queries meet more than k equal top scores
     assert (es[: NQ // 2, k - 1] == es[: NQ // 2, 0]).sum() >= NQ // 4
-    for qtile in (64, 128):
+    for qtile in (64, 128, 256):
         for grid in (0, 8):
             for nq in (16, NQ):
                 say(f"floor: k={k} qtile={qtile} grid={grid} nq={nq}")
