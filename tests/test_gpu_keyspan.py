@@ -9,8 +9,8 @@ form.  Each query's own row is planted at local ids 2^20 - 1 - q and at the
 last ids of every part (before either side encodes), so those vectors are
 the query's only exact matches and the top of every result comes from the
 highest local ids.  Both databases are compared with the oracle's exhaustive
-top-k (its own codes of the same rows), at k = 50 and 100, with a 64-query
-tile on a grid of 8 workgroups (one query tile, 8 parts)."""
+top-k (its own codes of the same rows), at k = 50 and 100, with 64- and
+256-query tiles on a grid of 8 workgroups (one query tile, 8 parts)."""
 import sys
 
 import numpy as np
@@ -82,10 +82,12 @@ def test_part_of_two_to_the_twenty(tq, o, ntiles):
     for k in (50, 100):
         say(f"key span: ntiles={ntiles} k={k} oracle top-k")
         ei, es = o.knn(VQ, V, k)
-        say(f"key span: ntiles={ntiles} k={k} matrix engine, 8 parts of {(ntiles + 7) // 8} tiles")
-        ids, sc = tq.tq_search_knn(db, qc, k, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_MATRIX, qtile=64, grid=8)
-        torch.cuda.synchronize()
-        assert np.array_equal(sc.cpu().numpy(), es) and np.array_equal(ids.cpu().numpy(), ei), (ntiles, k)
+        for qtile in (64, 256):
+            say(f"key span: ntiles={ntiles} k={k} qtile={qtile} matrix engine, 8 parts of {(ntiles + 7) // 8} tiles")
+            ids, sc = tq.tq_search_knn(db, qc, k, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_MATRIX, qtile=qtile,
+                                       grid=8)
+            torch.cuda.synchronize()
+            assert np.array_equal(sc.cpu().numpy(), es) and np.array_equal(ids.cpu().numpy(), ei), (ntiles, k, qtile)
         # the planted rows lead every result, highest local ids included
         for q in range(NQ):
             mine = sorted(i for i, qq in plant.items() if qq == q)
