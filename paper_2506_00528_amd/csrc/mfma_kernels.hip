@@ -466,8 +466,8 @@ __device__ __forceinline__ uint64_t group_entry(uint64_t v, int gbase, int p) {
 
 // SAMPLE: the sample pass of the k > 16 scan -- tiles tile_lo + i tstride
 // only, i = 0, 1, ..., split over this grid like a database of that many tiles
-// (sample_split); its own instantiation, so that the full scan keeps its
-// registers.
+// (sample_split), with lists of sample_list_len(parts, k) keys; its own
+// instantiation, so that the full scan keeps its registers.
 template <int NC, int RB, int WV, bool SAMPLE>
 __global__ __launch_bounds__(64 * WV, RB * WV <= 8 ? 8 / WV : 1) void scan_mfma_group_kernel(const uint4 *__restrict__ tiles, int64_t n,
                                                                     const uint32_t *__restrict__ qprep,
@@ -495,7 +495,8 @@ __global__ __launch_bounds__(64 * WV, RB * WV <= 8 ? 8 / WV : 1) void scan_mfma_
   const int64_t tpp = split->tiles_per_part;
   const int64_t tile_lo = split->tile_lo, tile_hi = split->tile_hi;
   const int items = nqt * parts;
-  const int km1 = k - 1;
+  const int lk = SAMPLE ? sample_list_len(parts, k) : k;  // keys per list
+  const int km1 = lk - 1;
 
   for (int item = blockIdx.x; item < items; item += gridDim.x) {
     int qt, part;
@@ -617,8 +618,8 @@ __global__ __launch_bounds__(64 * WV, RB * WV <= 8 ? 8 / WV : 1) void scan_mfma_
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int qi = rb * 16 + 4 * grp + i;
-        if (qi < nact && col < k)
-          partial[(static_cast<int64_t>(q0 + qi) * parts + part) * k + col] = list[rb][i].v;
+        if (qi < nact && col < lk)
+          partial[(static_cast<int64_t>(q0 + qi) * parts + part) * lk + col] = list[rb][i].v;
       }
   }
 }
@@ -627,7 +628,7 @@ __global__ __launch_bounds__(64 * WV, RB * WV <= 8 ? 8 / WV : 1) void scan_mfma_
 // Sample floor for k > 16
 // ---------------------------------------------------------------------------
 //
-// The sample pass keeps the top 16 keys of every (query, part) of every
+// The sample pass keeps the top 8 or 16 keys of every (query, part) of every
 // stride-th tile.  Those keys are database keys, so if at least k of them score
 // >= s, the query's k-th key overall scores >= s and no key scoring below s
 // can be in its result.  One workgroup per query counts the sample keys per
@@ -640,7 +641,7 @@ constexpr int kBins = kBinsPerThread * kFloorBlock;         // score s -> bin s 
 
 __global__ __launch_bounds__(kFloorBlock) void sample_floor_kernel(const uint64_t *__restrict__ sp,
                                                                    const BatchParams *__restrict__ prm, int qtile,
-                                                                   int grid, int tstride, int lk, int k,
+                                                                   int grid, int tstride, int k,
                                                                    uint64_t *__restrict__ floor) {
   __shared__ int hist[kBins];
   __shared__ int chunk[kFloorBlock];
@@ -651,7 +652,7 @@ __global__ __launch_bounds__(kFloorBlock) void sample_floor_kernel(const uint64_
   const int j = threadIdx.x;
   for (int i = j; i < kBins; i += kFloorBlock) hist[i] = 0;
   __syncthreads();
-  const int64_t cnt = static_cast<int64_t>(b.parts) * lk;
+  const int64_t cnt = static_cast<int64_t>(b.parts) * sample_list_len(b.parts, k);
   const uint64_t *src = sp + static_cast<int64_t>(q) * cnt;
   for (int64_t i = j; i < cnt; i += kFloorBlock) {
     const uint64_t key = src[i];
@@ -740,13 +741,12 @@ hipError_t scan_mfma_launch_nc(const DbDev &db, const uint32_t *qprep, const Bat
     if (!sample.floor || sample.bucket < 1) return hipErrorInvalidValue;
     // the sample takes the group kernel of the same query tile, so both
     // passes and the floor kernel split the batch alike
-    hipError_t e = qtile == 64 ? launch_g<NC, 1>(db, qprep, prm, kGroupMaxK, grid, partial, s, sample.stride)
-                   : qtile == 128 ? launch_g<NC, 1, 8>(db, qprep, prm, kGroupMaxK, grid, partial, s, sample.stride)
-                                  : launch_g<NC, 2, 8>(db, qprep, prm, kGroupMaxK, grid, partial, s, sample.stride);
+    hipError_t e = qtile == 64 ? launch_g<NC, 1>(db, qprep, prm, k, grid, partial, s, sample.stride)
+                   : qtile == 128 ? launch_g<NC, 1, 8>(db, qprep, prm, k, grid, partial, s, sample.stride)
+                                  : launch_g<NC, 2, 8>(db, qprep, prm, k, grid, partial, s, sample.stride);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(sample_floor_kernel, dim3(sample.bucket), dim3(kFloorBlock), 0, s,
-                       static_cast<const uint64_t *>(partial), prm, qtile, grid, sample.stride, kGroupMaxK, k,
-                       sample.floor);
+                       static_cast<const uint64_t *>(partial), prm, qtile, grid, sample.stride, k, sample.floor);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     floor = sample.floor;
   }

@@ -108,6 +108,10 @@ __host__ __device__ inline void sample_split(BatchParams &b, const BatchParams &
   b.bound = nullptr;
 }
 
+// Keys kept per (query, part) by a sample pass for a search of k: 8 where the
+// parts can hold at least 2k of them, else 16 (kGroupMaxK).
+__host__ __device__ inline int sample_list_len(int parts, int k) { return parts * 8 >= 2 * k ? 8 : 16; }
+
 // Bounds that hold for every split of up to `nq` queries on `grid`
 // workgroups: the parts of one query, and the (query, part) lists of a call.
 inline int batch_max_parts(int grid) { return kMaxRounds * grid + kXcds; }
@@ -133,11 +137,11 @@ bool mfma_supported(int k, int qtile);
 // max_part_tiles: an upper bound on prm->tiles_per_part for this launch (the
 // k > 16 scan keys ids relative to their part where parts span <= 2^20 vectors).
 // Sample floor (k > 16 only; sample.stride == 0: none): a first pass scores
-// every stride-th tile with 16-key lists, a per-query histogram of those keys
-// gives the largest score s that at least k of them reach (no key of the
-// final top-k scores below s), and the full scan drops keys scoring below s.
-// sample.floor holds one key per query of the bucket; the sample's lists
-// reuse `partial` (16 < k keys per list).
+// every stride-th tile with lists of sample_list_len keys, a per-query
+// histogram of those keys gives the largest score s that at least k of them
+// reach (no key of the final top-k scores below s), and the full scan drops
+// keys scoring below s.  sample.floor holds one key per query of the bucket;
+// the sample's lists reuse `partial` (at most 16 < k keys per list).
 struct MfmaSample {
   int stride = 0;
   int bucket = 0;
