@@ -213,7 +213,7 @@ def run_batching(tq, torch, db, queries, x, n, W, plain_qps, args, log):
             "popcount_engine": {"seconds": round(dt_pop, 3), "qps": round(total_q / dt_pop, 1),
                                 "vs_plain": round(total_q / dt_pop / plain_qps, 2)},
             "same_results_as_plain": ok,
-            "roofline": {"kernel": "scan_mfma_group_kernel (k <= 16) + scan_mfma_kernel", "bound": "mfma", "achieved": round(tflops, 1),
+            "roofline": {"kernel": "scan_mfma_group_kernel (k <= 16); sample pass + sample_floor_kernel + scan_mfma_kernel (k > 16)", "bound": "mfma", "achieved": round(tflops, 1),
                          "peak": fp4_peak, "unit": "TFLOP/s", "frac": round(tflops / fp4_peak, 4),
                          "flops_per_pair": 2 * d_pad, "batches": len(on_matrix), "launches": launches_m,
                          "avg_launch_ms": round(kms_m / max(1, launches_m), 4),
@@ -706,7 +706,7 @@ def main():
         tflops = 2.0 * B * n * d_pad / (avg_launch_ms * 1e-3) / 1e12
         result["hbm_gbps"] = None
         result["hbm_frac"] = None
-        result["roofline"] = {"kernel": "scan_mfma_group_kernel (k <= 16) + scan_mfma_kernel", "bound": "mfma", "achieved": round(tflops, 1),
+        result["roofline"] = {"kernel": "scan_mfma_group_kernel (k <= 16); sample pass + sample_floor_kernel + scan_mfma_kernel (k > 16)", "bound": "mfma", "achieved": round(tflops, 1),
                               "peak": 10100.0, "unit": "TFLOP/s", "frac": round(tflops / 10100.0, 4),
                               "traffic": None, "flops_per_pair": 2 * d_pad,
                               "avg_launch_ms": round(avg_launch_ms, 5), "launches": launches}
