@@ -5,6 +5,7 @@
 // every tile, keep the part count a multiple of the XCD count, take at most
 // kMaxRounds rounds of the grid unless the query tiles alone need more (the
 // 8-part floor), and never use fewer parts than one round of the grid holds.
+// The same for the sample split of the matrix engine (see below).
 // Prints "OK <cases>" or the first violation.
 #include <cstdio>
 
@@ -48,6 +49,38 @@ int main() {
             }
           }
         }
+  // The matrix engine's sample pass (every 16th tile, k > 16): its split of
+  // the sample tiles fits the same list buffers as the full scan's, every
+  // sample tile is a database tile of the range, and its lists (8 or 16 keys,
+  // fewer than k) hold at least 2k keys per query when they are 8 long.
+  for (int qt : {64, 128, 256})
+    for (int grid : grids)
+      for (long long span : spans)
+        for (int nq = 1; nq <= 1024; ++nq)
+          for (int k : {17, 64, 100, 128}) {
+            const long long lo = 3;
+            const int stride = 16;
+            tqi::BatchParams b, sb;
+            tqi::batch_split(b, nq, qt, grid, lo, lo + span);
+            tqi::sample_split(sb, b, qt, grid, stride);
+            ++cases;
+            const long long stiles = (span + stride - 1) / stride;
+            const int lk = tqi::sample_list_len(sb.parts, k);
+            const char *bad = nullptr;
+            if (sb.nq != nq || sb.tile_lo != 0 || sb.tile_hi != stiles) bad = "sample range";
+            else if (lo + (stiles - 1) * stride >= lo + span) bad = "sample tile past the range";
+            else if (sb.tiles_per_part * sb.parts < stiles) bad = "sample tiles not covered";
+            else if (static_cast<size_t>(nq) * sb.parts > tqi::batch_max_lists(qt, grid, nq))
+              bad = "more sample lists than the buffers";
+            else if (!(lk == 8 || lk == 16) || lk >= k) bad = "sample list length";
+            else if (lk == 8 && sb.parts * 8LL < 2LL * k) bad = "8-key sample lists hold fewer than 2k keys";
+            else if (sb.bound || sb.running || sb.ids || sb.scores || sb.slots) bad = "sample split keeps outputs";
+            if (bad) {
+              std::printf("FAIL %s: nq=%d qtile=%d grid=%d tiles=%lld k=%d parts=%d\n", bad, nq, qt, grid, span, k,
+                          sb.parts);
+              return 1;
+            }
+          }
   std::printf("OK %lld\n", cases);
   return 0;
 }
