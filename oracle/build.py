@@ -20,7 +20,7 @@ def library_path(mutant: int = 0, out_dir: str | None = None, sanitize: bool = F
 
 
 # AddressSanitizer + UndefinedBehaviorSanitizer (gcc): a process that loads
-# this build needs gcc's libasan preloaded (asan_runtime()).
+# the sanitized library needs gcc's libasan preloaded (asan_runtime()).
 SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-fno-sanitize-recover=undefined", "-g"]
 
 

@@ -1,5 +1,5 @@
-"""Locate / build the HIP library for the tests (never builds on a GPU machine
-if a library is already there)."""
+"""Locate the HIP library for the tests; it is built only where none exists
+yet (a library already built is loaded as it is)."""
 import os
 import re
 
