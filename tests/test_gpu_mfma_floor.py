@@ -82,3 +82,25 @@ def test_floor_matches_oracle(tq, o, setup, k):
                 torch.cuda.synchronize()
                 assert np.array_equal(sc.cpu().numpy(), es[:nq]), (k, qtile, grid, nq)
                 assert np.array_equal(ids.cpu().numpy(), ei[:nq]), (k, qtile, grid, nq)
+
+
+def test_floor_graph_replays(tq, o, setup):
+    """One captured graph (bucket of 128 queries, k = 100) replayed with
+    different query counts and offsets, other GPU work in between: the sample
+    pass, the floor kernel and the full scan read the per-call parameters the
+    prep kernel writes, so every replay must give the oracle's result."""
+    db, qc, V, VQ = setup
+    rng = np.random.default_rng(11)
+    junk = torch.zeros(1 << 20, device="cuda")
+    k = 100
+    for rep in range(4):
+        nq = int(rng.integers(65, 129))
+        q0 = int(rng.integers(0, NQ - nq + 1))
+        say(f"floor graph replay {rep}: nq={nq} q0={q0}")
+        junk.add_(1.0)
+        junk.sum().item()
+        ids, sc = tq.tq_search_knn(db, qc[q0:q0 + nq], k, path=tq.TQ_PATH_BATCHED, engine=tq.TQ_ENGINE_MATRIX,
+                                   qtile=64)
+        torch.cuda.synchronize()
+        ei, es = o.knn(VQ[q0:q0 + nq], V, k)
+        assert np.array_equal(sc.cpu().numpy(), es) and np.array_equal(ids.cpu().numpy(), ei), rep
