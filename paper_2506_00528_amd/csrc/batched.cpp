@@ -156,7 +156,7 @@ int mfma_resident_per_cu(int k, int qtile) {
 
 int default_matrix_qtile(int k, int bucket) {
   if (k <= tqi::kGroupMaxK) return bucket >= 512 ? 256 : bucket >= 128 ? 128 : 64;
-  return bucket >= 512 ? 256 : bucket >= 256 ? 128 : 64;
+  return bucket >= 256 ? 256 : bucket >= 128 ? 128 : 64;
 }
 
 Shape default_shape(const tq_db *db, int k, int bucket) {
@@ -168,7 +168,9 @@ Shape default_shape(const tq_db *db, int k, int bucket) {
   if (s.engine == TQ_ENGINE_MATRIX) {
     // (N = 1e7, d = 1024, k = 10: 1 024 queries 5.2 / 5.3 / 7.4 ms on 256 /
     // 128 / 64-query tiles, 256 queries 1.8 / 1.6 / 2.2 ms; k = 100, 1 024
-    // queries: 6.8 / 8.8 ms on 256 / 128, 512 queries 3.6 / 4.8 ms)
+    // queries: 6.6 / 8.8 ms on 256 / 128, 512 queries 3.5 / 4.8 ms, 160
+    // queries 1.7 / 2.4 / 2.2 ms on 256 / 128 / 64, 100 queries 1.5 / 1.2 /
+    // 1.4 ms, 64 queries 1.4 / 1.1 / 0.8 ms)
     s.qtile = default_matrix_qtile(k, bucket);
     s.grid = cu * mfma_resident_per_cu(k, s.qtile);
   } else {
